@@ -1,0 +1,131 @@
+/*
+ * Stream VByte reference codec: plain, scalar, one byte at a time.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the GPU library, and the GPU library never calls it.
+ *
+ * What it computes (Lemire, Kurz, Rupp, "Stream VByte: Faster Byte-Oriented
+ * Integer Compression", Information Processing Letters 2018):
+ *
+ *  - Byte length of an integer x in [0, 2^32): ceil(log_256(x + 1)) bytes,
+ *    one of {1, 2, 3, 4}; stored as a 2-bit code (Section 3, the varint-GB
+ *    description, and Fig. 1).  x = 0 is given length 1, the only length in
+ *    {1,2,3,4} that can hold it.
+ *  - Four 2-bit codes per control byte; integer 4b+j uses bits [2j, 2j+1] of
+ *    control byte b, code = length - 1 (Fig. 1 and Fig. 3; the bit order is a
+ *    convention the paper leaves open, taken least-significant-first here).
+ *  - All ceil(N/4) control bytes come first, then the data bytes of all
+ *    integers, back to back (Section 4, Fig. 3).  N is stored out of band.
+ *  - Each integer's data bytes are little-endian (the decoder of Section 4
+ *    shuffles bytes into little-endian 32-bit lanes).
+ *  - Differential coding (Section 2, "Differential Coding", and Section 5):
+ *    the encoder stores d_i = x_i - x_{i-1} with x_0 = start, the decoder
+ *    rebuilds x_i = d_i + x_{i-1}.  Both run modulo 2^32, so every array of
+ *    32-bit integers round-trips, sorted or not.
+ *
+ * Every loop below visits one integer at a time in stream order; there is no
+ * lookup table, no blocking and no vector code.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+/* Byte length of v (Section 3): the smallest L in {1,2,3,4} with
+ * v < 256^L, written as the chain of comparisons it is. */
+uint32_t svbref_length(uint32_t v)
+{
+    if (v < (1u << 8)) return 1;
+    if (v < (1u << 16)) return 2;
+    if (v < (1u << 24)) return 3;
+    return 4;
+}
+
+/* Number of data bytes described by one control byte whose four codes are
+ * all in use (Section 4: between 4 and 16). */
+uint32_t svbref_control_bytes_of(uint8_t control)
+{
+    uint32_t total = 0;
+    for (int j = 0; j < 4; ++j) total += ((control >> (2 * j)) & 3u) + 1u;
+    return total;
+}
+
+/* Histogram of svbref_length over every v in [0, 2^32) (hist[L-1] += 1).
+ * Used to pin the length rule against its closed form. */
+void svbref_length_histogram(uint64_t hist[4])
+{
+    hist[0] = hist[1] = hist[2] = hist[3] = 0;
+    uint32_t v = 0;
+    do {
+        hist[svbref_length(v) - 1] += 1;
+        v += 1;
+    } while (v != 0);
+}
+
+/* Encode n integers (Section 4).  If delta != 0 the stored values are the
+ * successive differences modulo 2^32 with x_0 = start (Section 2).
+ * out must hold at least ceil(n/4) + 4n bytes.  Returns the number of bytes
+ * written: ceil(n/4) + sum of the byte lengths. */
+uint64_t svbref_encode(const uint32_t *x, uint64_t n, int delta, uint32_t start,
+                       uint8_t *out)
+{
+    uint64_t ncontrol = (n + 3) / 4;
+    memset(out, 0, (size_t)ncontrol);
+    uint64_t p = ncontrol;
+    uint32_t prev = start;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t v = delta ? (uint32_t)(x[i] - prev) : x[i];
+        prev = x[i];
+        uint32_t len = svbref_length(v);
+        out[i / 4] |= (uint8_t)((len - 1u) << (2u * (uint32_t)(i % 4)));
+        for (uint32_t k = 0; k < len; ++k) out[p + k] = (uint8_t)((v >> (8u * k)) & 0xFFu);
+        p += len;
+    }
+    return p;
+}
+
+/* Decode n integers from in[0, in_bytes) (Section 4: one pointer walks the
+ * control bytes, one walks the data bytes and advances by each integer's
+ * length).  With delta != 0 the decoded values are deltas and the output is
+ * their running sum modulo 2^32 starting from start (Section 2).
+ * Returns the number of bytes consumed, or -1 if the stream is shorter than
+ * the control stream or than the data its control bytes describe.  Codes of
+ * the unused fields of a partial last control byte are never read. */
+int64_t svbref_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, int delta,
+                      uint32_t start, uint32_t *out)
+{
+    uint64_t ncontrol = (n + 3) / 4;
+    if (in_bytes < ncontrol) return -1;
+    uint64_t p = ncontrol;
+    uint32_t prev = start;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t code = (in[i / 4] >> (2u * (uint32_t)(i % 4))) & 3u;
+        uint32_t len = code + 1u;
+        if (p + len > in_bytes) return -1;
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < len; ++k) v |= (uint32_t)in[p + k] << (8u * k);
+        p += len;
+        if (delta) {
+            prev = prev + v;
+            out[i] = prev;
+        } else {
+            out[i] = v;
+        }
+    }
+    return (int64_t)p;
+}
+
+/* Size of the stream svbref_encode would write, without writing it
+ * (ceil(n/4) control bytes plus the byte lengths, Section 3). */
+uint64_t svbref_encoded_size(const uint32_t *x, uint64_t n, int delta, uint32_t start)
+{
+    uint64_t total = (n + 3) / 4;
+    uint32_t prev = start;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t v = delta ? (uint32_t)(x[i] - prev) : x[i];
+        prev = x[i];
+        total += svbref_length(v);
+    }
+    return total;
+}

@@ -1,0 +1,270 @@
+"""Pins for the oracle (C and pure Python) against what the paper and arithmetic fix.
+
+Each test names the passage it follows.  None of these tests touch a GPU; they
+pin the oracle before it is trusted to judge the HIP library.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ref
+from paper_1709_08990_amd import inputs
+
+MASK32 = 0xFFFFFFFF
+BOUNDS = [(0, 1 << 8), (1 << 8, 1 << 16), (1 << 16, 1 << 24), (1 << 24, 1 << 32)]
+
+
+def lengths_by_top_byte(x):
+    """Byte length as 1 + index of the highest non-zero little-endian byte (1 for zero):
+    a formulation unrelated to the comparison chain, bit_length or clz."""
+    b = np.ascontiguousarray(x, dtype="<u4").view(np.uint8).reshape(-1, 4)
+    nz = b != 0
+    top = np.where(nz.any(axis=1), 3 - np.argmax(nz[:, ::-1], axis=1), 0)
+    return top + 1
+
+
+# ---------------------------------------------------------------- P1, P2: paper figures
+
+def _fig3(golden_dir):
+    with open(os.path.join(golden_dir, "fig3_stream_example.json")) as f:
+        return json.load(f)
+
+
+def test_fig3_sizes(golden_dir):
+    """Fig. 3 (Section 4): the eight integers take 2 control bytes and 13 data bytes."""
+    g = _fig3(golden_dir)
+    x = np.array(g["values"], dtype=np.uint32)
+    s = oracle.encode(x)
+    assert s.size == g["total_bytes"] == g["control_bytes"] + g["data_bytes"]
+    assert oracle.encoded_size(x) == g["total_bytes"]
+    assert len(ref.encode(g["values"])) == g["total_bytes"]
+
+
+def test_fig3_codes_and_bytes(golden_dir):
+    """Fig. 3: printed codes per integer and printed data bytes, under the stated reading
+    (codes in integer order, least significant field first; bytes little-endian in memory)."""
+    g = _fig3(golden_dir)
+    x = np.array(g["values"], dtype=np.uint32)
+    s = oracle.encode(x)
+    ctrl, data = s[:g["control_bytes"]], s[g["control_bytes"]:]
+    for b, printed in enumerate(g["codes_as_printed"]):
+        fields = printed.split("|")
+        for j, f in enumerate(fields):
+            assert (int(ctrl[b]) >> (2 * j)) & 3 == int(f, 2), (b, j)
+    expect = []
+    for printed in g["data_as_printed"]:
+        expect.extend(reversed([int(h, 16) for h in printed]))
+    assert list(data) == expect
+    vals, used = oracle.decode(s, x.size)
+    assert list(vals) == g["values"] and used == g["total_bytes"]
+    assert ref.decode(bytes(s), x.size) == g["values"]
+
+
+def test_fig1_block_sizes(golden_dir):
+    """Fig. 1a/1b (Section 3): per-block sizes 9 and 6 bytes; a Stream VByte stream of one
+    block is the same control byte plus the same data bytes."""
+    with open(os.path.join(golden_dir, "fig1_varint_gb_blocks.json")) as f:
+        g = json.load(f)
+    for blk in g["blocks"]:
+        x = np.array(blk["values"], dtype=np.uint32)
+        assert oracle.encode(x).size == blk["total_bytes"]
+        assert [oracle.length(v) for v in blk["values"]] == blk["lengths"]
+        assert [ref.byte_length(v) for v in blk["values"]] == blk["lengths"]
+
+
+# ---------------------------------------------------------------- P3: lengthTable facts
+
+def test_control_byte_lengths():
+    """Section 4: a control byte describes between 4 and 16 data bytes; all-zero gives 4."""
+    table = [oracle.control_bytes_of(c) for c in range(256)]
+    assert table[0] == 4 and table[255] == 16
+    assert min(table) == 4 and max(table) == 16
+    # each of the four fields takes each code 64 times: 256*4 + 4*64*(0+1+2+3)
+    assert sum(table) == 2560
+
+
+def test_control_byte_brute_force():
+    """Every control byte value is produced by the encoder for the matching block of four
+    lengths, and the block's data size equals the control byte's described length."""
+    for c in range(256):
+        codes = [(c >> (2 * j)) & 3 for j in range(4)]
+        x = np.array([BOUNDS[k][0] + 1 if k else 7 for k in codes], dtype=np.uint32)
+        s = oracle.encode(x)
+        assert s[0] == c
+        assert s.size - 1 == oracle.control_bytes_of(c)
+
+
+# ---------------------------------------------------------------- P4: prefix sum
+
+def test_prefix_sum_example(golden_dir):
+    """Section 2 'Differential Coding': deltas (3,4,12,1) decode to (3,7,19,20)."""
+    with open(os.path.join(golden_dir, "prefix_sum_example.json")) as f:
+        g = json.load(f)
+    d = np.array(g["deltas"], dtype=np.uint32)
+    s = oracle.encode(d)
+    vals, _ = oracle.decode(s, d.size, delta=True, start=0)
+    assert list(vals) == g["prefix_sum"]
+    # the delta encoder of the prefix sums stores exactly the deltas
+    s2 = oracle.encode(np.array(g["prefix_sum"], dtype=np.uint32), delta=True, start=0)
+    assert bytes(s2) == bytes(s)
+    assert oracle.decode(s2, 4)[0].tolist() == g["deltas"]
+    # the example's two log-step shift-and-add rounds reach the same vector
+    v = list(g["deltas"])
+    v1 = [a + b for a, b in zip(v, [0] + v[:-1])]
+    assert v1 == g["after_first_shift_add"]
+    v2 = [a + b for a, b in zip(v1, [0, 0] + v1[:-2])]
+    assert v2 == g["prefix_sum"]
+
+
+@pytest.mark.parametrize("start", [0, 1, 0xFFFFFFFF, 123456789])
+def test_delta_decode_is_wrapping_cumsum(start):
+    """Delta decode equals numpy's uint32 cumulative sum (which wraps modulo 2^32) plus start."""
+    d = inputs.random_u32(10_001, seed=11)
+    s = oracle.encode(d)
+    vals, _ = oracle.decode(s, d.size, delta=True, start=start)
+    expect = (np.cumsum(d, dtype=np.uint32) + np.uint32(start)).astype(np.uint32)
+    assert np.array_equal(vals, expect)
+
+
+# ---------------------------------------------------------------- P5: size invariant
+
+@pytest.mark.parametrize("gen", ["uniform", "stress", "random"])
+def test_size_invariant(gen):
+    """Section 3/4: size = ceil(n/4) + sum of byte lengths."""
+    if gen == "uniform":
+        x = inputs.uniform_lengths(100_003, seed=1)
+    elif gen == "stress":
+        x = inputs.stress_lengths(65_537, seed=3)
+    else:
+        x = inputs.random_u32(4_099, seed=5)
+    s = oracle.encode(x)
+    expect = (x.size + 3) // 4 + int(lengths_by_top_byte(x).sum())
+    assert s.size == expect == oracle.encoded_size(x)
+
+
+def test_uniform_workload_lengths_are_uniform():
+    """The byte-length mix of the uniform workload is what it claims (sanity for the recipe)."""
+    x = inputs.uniform_lengths(400_000, seed=1)
+    h = np.bincount(lengths_by_top_byte(x), minlength=5)[1:] / x.size
+    assert np.allclose(h, 0.25, atol=0.01)
+
+
+# ---------------------------------------------------------------- P6: round trips
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 7, 8, 9, 1023, 4096, 4097, 100_003])
+def test_round_trip(n):
+    x = inputs.random_u32(n, seed=n + 1) >> np.uint32(n % 29)
+    for delta in (False, True):
+        s = oracle.encode(x, delta=delta, start=17)
+        vals, used = oracle.decode(s, n, delta=delta, start=17)
+        assert used == s.size
+        assert np.array_equal(vals, x)
+
+
+def test_docid_generator_reproduces_gaps():
+    """Delta coding of the sorted document ids (start 0) stores exactly the generator's gaps,
+    including across the wrap-arounds modulo 2^32."""
+    x, g = inputs.docids(1 << 20, seed=2)
+    assert int(np.sum(g, dtype=np.uint64)) > (1 << 32)  # the running sum wraps
+    s = oracle.encode(x, delta=True, start=0)
+    gaps, _ = oracle.decode(s, x.size)
+    assert np.array_equal(gaps, g)
+    back, _ = oracle.decode(s, x.size, delta=True, start=0)
+    assert np.array_equal(back, x)
+
+
+def test_posting_lists_round_trip():
+    vals, offs = inputs.posting_lists(m=300, total=30_000, cap=4096, seed=4)
+    lists = [vals[offs[i]:offs[i + 1]] for i in range(offs.size - 1)]
+    streams = oracle.encode_lists(lists, delta=True)
+    back = oracle.decode_lists(streams, [l.size for l in lists], delta=True)
+    for a, b in zip(lists, back):
+        assert np.array_equal(a, b)
+        assert np.all(np.diff(a.astype(np.int64)) > 0) and (a.size == 0 or a.max() < (1 << 31))
+
+
+# ---------------------------------------------------------------- P7: brute force
+
+def _boundary_values(L):
+    lo, hi = BOUNDS[L - 1]
+    return [lo, lo + 1, hi - 1]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6])
+def test_brute_force_length_patterns(n):
+    """All 4^n length patterns, each with boundary values, C oracle == Python oracle, both
+    directions, plain and delta."""
+    for pattern in itertools.product(range(1, 5), repeat=n):
+        for variant in range(3):
+            vals = [_boundary_values(L)[(i + variant) % 3] for i, L in enumerate(pattern)]
+            x = np.array(vals, dtype=np.uint32)
+            s = oracle.encode(x)
+            assert bytes(s) == ref.encode(vals)
+            assert s.size == (n + 3) // 4 + sum(pattern)
+            assert oracle.decode(s, n)[0].tolist() == vals
+            if variant == 0:
+                sd = oracle.encode(x, delta=True, start=5)
+                assert bytes(sd) == ref.encode(vals, delta=True, start=5)
+                assert oracle.decode(sd, n, delta=True, start=5)[0].tolist() == vals
+
+
+def test_all_control_bytes_with_tails():
+    """Every control byte value with 1, 2 or 3 integers in use: unused fields are ignored."""
+    data = bytes(range(1, 17))
+    for c in range(256):
+        for r in (1, 2, 3, 4):
+            stream = bytes([c]) + data
+            got = oracle.decode(np.frombuffer(stream, dtype=np.uint8), r)[0].tolist()
+            assert got == ref.decode(stream, r)
+            masked = c & ((1 << (2 * r)) - 1)
+            assert got == ref.decode(bytes([masked]) + data, r)
+
+
+# ---------------------------------------------------------------- P8: length rule
+
+def test_length_rule_boundaries():
+    for L, (lo, hi) in enumerate(BOUNDS, start=1):
+        for v in (lo, lo + 1, hi - 2, hi - 1):
+            if v < 0:
+                continue
+            assert oracle.length(v) == ref.byte_length(v) == L
+            assert lengths_by_top_byte(np.array([v], dtype=np.uint32))[0] == L
+    assert oracle.length(0) == 1
+
+
+@pytest.mark.slow
+def test_length_rule_exhaustive():
+    """All 2^32 values: the count per byte length matches the closed form 256^L - 256^(L-1)
+    (with the zero value in the one-byte class)."""
+    assert oracle.length_histogram() == [256, 65536 - 256, (1 << 24) - 65536, (1 << 32) - (1 << 24)]
+
+
+# ---------------------------------------------------------------- P9: random streams
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 13, 64, 1001])
+def test_random_stream_fuzz(n):
+    """Random control bytes (with garbage in unused tail fields) followed by exactly the data
+    they describe decode identically in both oracles; one byte less is reported as corrupt."""
+    k = (n + 3) // 4
+    ctrl = inputs.random_bytes(k, seed=100 + n)
+    need = sum(((int(ctrl[i // 4]) >> (2 * (i % 4))) & 3) + 1 for i in range(n))
+    data = inputs.random_bytes(need, seed=200 + n)
+    stream = np.concatenate([ctrl, data])
+    vals, used = oracle.decode(stream, n)
+    assert used == stream.size
+    assert vals.tolist() == ref.decode(bytes(stream), n)
+    dv, _ = oracle.decode(stream, n, delta=True, start=9)
+    assert dv.tolist() == ref.decode(bytes(stream), n, delta=True, start=9)
+    with pytest.raises(ValueError):
+        oracle.decode(stream[:-1], n)
+    with pytest.raises(ValueError):
+        ref.decode(bytes(stream[:-1]), n)
+
+
+def test_truncated_control_stream_is_corrupt():
+    with pytest.raises(ValueError):
+        oracle.decode(np.zeros(1, dtype=np.uint8), 5)
