@@ -1,0 +1,173 @@
+/*
+ * svb.h -- Stream VByte on AMD Instinct MI355X (gfx950): C ABI of libsvb.so.
+ *
+ * Format (Lemire, Kurz, Rupp, "Stream VByte: Faster Byte-Oriented Integer
+ * Compression", Section 4 and Fig. 3).  A stream of n unsigned 32-bit
+ * integers is one byte buffer:
+ *
+ *     [ control stream: ceil(n/4) bytes | data stream: sum of L_i bytes ]
+ *
+ *  - L_i = max(1, ceil(log_256(x_i + 1))) in {1,2,3,4} (Section 3).
+ *  - Control byte b holds the 2-bit codes L_i - 1 of integers 4b..4b+3,
+ *    integer 4b+j in bits [2j, 2j+1].  Unused fields of a partial last
+ *    control byte are written as 0 and ignored when read.
+ *  - Integer i occupies L_i consecutive data bytes, little-endian.
+ *  - n is not stored in the stream; every call takes it as an argument.
+ *
+ * Differential ("delta") variant (Section 2, "Differential Coding", and
+ * Section 5): the stored values are d_i = x_i - x_{i-1} modulo 2^32 with
+ * x_{-1} = start; decoding returns the running sum modulo 2^32 from start.
+ * Any uint32 array round-trips, sorted or not.
+ *
+ * Conventions shared by every call:
+ *  - Every buffer pointer is a DEVICE pointer on the current HIP device,
+ *    owned by the caller.  The library never frees or retains them.
+ *  - uint32_t arrays must be 4-byte aligned; byte streams have no alignment
+ *    requirement.  uint64_t arrays must be 8-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream: results are valid after the
+ *    stream is synchronised.  Argument errors are returned synchronously.
+ *  - Calls on different streams may run concurrently: the library keeps a
+ *    separate scratch workspace per (device, stream).  Calls on one stream
+ *    are ordered by the stream.
+ *  - The only library-owned memory is that scratch workspace (a few counters
+ *    and one 8-byte status word per tile of 4096 integers; grown on demand,
+ *    freed by svb_release_workspace).
+ *  - Return value: SVB_OK (0) or a negative svb_status.  The library never
+ *    aborts the process.
+ */
+#ifndef SVB_H
+#define SVB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum svb_status {
+    SVB_OK = 0,
+    SVB_ERR_INVALID = -1,   /* bad argument: null pointer with n > 0, misaligned uint32 array,
+                               in_bytes smaller than the control stream, n too large */
+    SVB_ERR_CORRUPT = -2,   /* reported through the `err` word of decode calls, see below */
+    SVB_ERR_HIP = -3,       /* a HIP runtime call failed (launch, allocation of scratch) */
+    SVB_ERR_NOMEM = -4      /* scratch workspace could not be allocated */
+};
+
+/* Value a decode kernel writes to the caller's device `err` word when the
+ * control bytes describe more data than in_bytes holds. */
+#define SVB_DECODE_CORRUPT 1u
+
+/* Largest n accepted by the single-stream calls (2^40 integers). */
+#define SVB_MAX_N (((uint64_t)1) << 40)
+
+/* ceil(n/4): size of the control stream (Section 4). */
+uint64_t svb_control_bytes(uint64_t n);
+
+/* ceil(n/4) + 4n: the largest stream n integers can need (every L_i = 4). */
+uint64_t svb_max_compressed_bytes(uint64_t n);
+
+/*
+ * svb_encode -- Section 4 (format) and Section 3 (byte lengths).
+ *   n          number of integers in `in`.
+ *   in         device uint32[n], 4-byte aligned.
+ *   out        device byte buffer of at least svb_max_compressed_bytes(n)
+ *              bytes; receives the stream.  Bytes past the stream's size are
+ *              not written.
+ *   out_bytes  device uint64: receives the stream size ceil(n/4) + sum L_i.
+ *              May be NULL.
+ * The encoding is unique (minimal lengths), so the output is byte-exact.
+ */
+int svb_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, void *stream);
+
+/* svb_delta_encode -- svb_encode of d_i = in[i] - in[i-1] (mod 2^32), in[-1] = start
+ * (Section 2, "Differential Coding"; Section 5). */
+int svb_delta_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start,
+                     uint64_t *out_bytes, void *stream);
+
+/*
+ * svb_decode -- Section 4 (the decoding procedure of Fig. 4, done as a
+ * parallel scan of control-byte lengths instead of a pointer chase).
+ *   n          number of integers to decode.
+ *   in         device stream of in_bytes bytes (no alignment requirement).
+ *   in_bytes   bytes readable at `in`; must be >= ceil(n/4).  The stream
+ *              may be followed by unrelated bytes (in_bytes larger than the
+ *              stream): they are never interpreted.
+ *   out        device uint32[n], 4-byte aligned.
+ *   err        device uint32 or NULL.  Set to SVB_DECODE_CORRUPT when the
+ *              control bytes describe more data bytes than in_bytes - ceil(n/4);
+ *              left untouched otherwise (initialise it to 0).  On corrupt
+ *              input the contents of `out` are unspecified, but no byte
+ *              outside [in, in + in_bytes) is read and nothing outside
+ *              out[0..n) is written.
+ */
+int svb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err,
+               void *stream);
+
+/* svb_delta_decode -- svb_decode followed by the running sum modulo 2^32
+ * starting from `start`, fused into the same pass (Section 2; Section 5). */
+int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out,
+                     uint32_t start, uint32_t *err, void *stream);
+
+/*
+ * Batched calls: m independent streams in one persistent launch with a
+ * device-side work queue.  The lists stand for posting lists (Section 5):
+ * many lists of very uneven lengths.  All array arguments are DEVICE arrays
+ * of m entries; the host never needs to read them.
+ *
+ * svb_encode_batch
+ *   counts[i]     integers in list i.
+ *   in_off[i]     index (in uint32 units) of list i's first integer in `in`.
+ *   out_off[i]    byte offset in `out` where stream i is written; the caller
+ *                 reserves svb_max_compressed_bytes(counts[i]) bytes there and
+ *                 reserved regions must not overlap.
+ *   out_bytes[i]  receives stream i's size (may be NULL).
+ *   starts        NULL: plain encoding.  Otherwise delta encoding of list i
+ *                 from starts[i].
+ */
+int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
+                     const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes,
+                     const uint32_t *starts, void *stream);
+
+/*
+ * svb_decode_batch
+ *   counts[i]     integers in list i.
+ *   in_off[i]     byte offset of stream i in `in`.
+ *   in_bytes[i]   bytes readable at in + in_off[i] (>= ceil(counts[i]/4)).
+ *   out_off[i]    index (uint32 units) where list i's integers are written;
+ *                 output ranges must not overlap.
+ *   starts        NULL: plain decoding.  Otherwise delta decoding of list i
+ *                 from starts[i].
+ *   err           device uint32 or NULL; set to SVB_DECODE_CORRUPT if any
+ *                 stream is corrupt (see svb_decode).
+ * The host-side checks cover the pointers only (the arrays live on the
+ * device); a short in_bytes[i] is reported through err.
+ */
+int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
+                     const uint64_t *in_bytes, const uint8_t *in, const uint64_t *out_off,
+                     uint32_t *out, const uint32_t *starts, uint32_t *err, void *stream);
+
+/* Message for a status code (static string). */
+const char *svb_strerror(int status);
+
+/* Frees every scratch workspace the library holds (all devices and streams).
+ * Synchronises the devices first.  Later calls allocate again. */
+void svb_release_workspace(void);
+
+/* Library version string. */
+const char *svb_version(void);
+
+/*
+ * Measurement helpers (not part of the codec): a plain copy kernel of the
+ * same launch style, used as the practical bandwidth ceiling and to scale
+ * hardware byte counters, and a kernel that writes `bytes` bytes of scratch
+ * to evict caches between timed runs.
+ */
+int svb_copy_u32(uint64_t n, const uint32_t *in, uint32_t *out, void *stream);
+int svb_fill_u32(uint64_t n, uint32_t *out, uint32_t value, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVB_H */

@@ -1,0 +1,189 @@
+"""Stream VByte on AMD Instinct MI355X: Python binding of libsvb.so.
+
+The functions named ``svb_*`` mirror the C ABI of ``include/svb.h`` one to one:
+they only marshal arguments (torch tensors -> device pointers, the current HIP
+stream) and raise ``SvbError`` on a non-zero status.  Every step of encoding
+and decoding runs in the HIP kernels of the library; there is no CPU path.
+
+The convenience wrappers ``encode`` / ``decode`` allocate outputs with torch.
+Integer arrays are torch ``int32`` tensors holding the uint32 bit patterns.
+"""
+import ctypes
+import os
+
+__all__ = [
+    "SvbError", "lib", "svb_control_bytes", "svb_max_compressed_bytes", "svb_encode",
+    "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_encode_batch", "svb_decode_batch",
+    "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
+    "encode", "decode", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
+SVB_DECODE_CORRUPT = 1
+
+_lib = None
+
+
+class SvbError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (what, _strerror(status), status))
+
+
+def lib():
+    """The loaded libsvb.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsvb.so is not built (%s); run `python -m paper_1709_08990_amd.build`"
+                               % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+        sigs = {
+            "svb_control_bytes": (u64, [u64]),
+            "svb_max_compressed_bytes": (u64, [u64]),
+            "svb_encode": (i32, [u64, vp, vp, vp, vp]),
+            "svb_delta_encode": (i32, [u64, vp, vp, u32, vp, vp]),
+            "svb_decode": (i32, [u64, vp, u64, vp, vp, vp]),
+            "svb_delta_decode": (i32, [u64, vp, u64, vp, u32, vp, vp]),
+            "svb_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "svb_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "svb_strerror": (ctypes.c_char_p, [i32]),
+            "svb_release_workspace": (None, []),
+            "svb_version": (ctypes.c_char_p, []),
+            "svb_copy_u32": (i32, [u64, vp, vp, vp]),
+            "svb_fill_u32": (i32, [u64, vp, u32, vp]),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(status):
+    try:
+        return lib().svb_strerror(int(status)).decode()
+    except Exception:  # pragma: no cover - only while reporting another error
+        return "status %d" % status
+
+
+def _ptr(t):
+    """Device address of a tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status, what):
+    if status != 0:
+        raise SvbError(status, what)
+    return status
+
+
+# ------------------------------------------------------------------ C ABI mirror
+
+def svb_control_bytes(n):
+    return int(lib().svb_control_bytes(int(n)))
+
+
+def svb_max_compressed_bytes(n):
+    return int(lib().svb_max_compressed_bytes(int(n)))
+
+
+def svb_encode(n, inp, out, out_bytes=None, stream=None):
+    return _check(lib().svb_encode(int(n), _ptr(inp), _ptr(out), _ptr(out_bytes), _stream(stream)),
+                  "svb_encode")
+
+
+def svb_delta_encode(n, inp, out, start=0, out_bytes=None, stream=None):
+    return _check(lib().svb_delta_encode(int(n), _ptr(inp), _ptr(out), int(start) & 0xFFFFFFFF,
+                                         _ptr(out_bytes), _stream(stream)), "svb_delta_encode")
+
+
+def svb_decode(n, inp, in_bytes, out, err=None, stream=None):
+    return _check(lib().svb_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), _ptr(err),
+                                   _stream(stream)), "svb_decode")
+
+
+def svb_delta_decode(n, inp, in_bytes, out, start=0, err=None, stream=None):
+    return _check(lib().svb_delta_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out),
+                                         int(start) & 0xFFFFFFFF, _ptr(err), _stream(stream)),
+                  "svb_delta_decode")
+
+
+def svb_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, stream=None):
+    return _check(lib().svb_encode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(inp), _ptr(out_off),
+                                         _ptr(out), _ptr(out_bytes), _ptr(starts), _stream(stream)),
+                  "svb_encode_batch")
+
+
+def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, err=None, stream=None):
+    return _check(lib().svb_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
+                                         _ptr(out_off), _ptr(out), _ptr(starts), _ptr(err),
+                                         _stream(stream)), "svb_decode_batch")
+
+
+def svb_strerror(status):
+    return _strerror(status)
+
+
+def svb_release_workspace():
+    lib().svb_release_workspace()
+
+
+def svb_version():
+    return lib().svb_version().decode()
+
+
+def svb_copy_u32(n, inp, out, stream=None):
+    return _check(lib().svb_copy_u32(int(n), _ptr(inp), _ptr(out), _stream(stream)), "svb_copy_u32")
+
+
+def svb_fill_u32(n, out, value, stream=None):
+    return _check(lib().svb_fill_u32(int(n), _ptr(out), int(value) & 0xFFFFFFFF, _stream(stream)),
+                  "svb_fill_u32")
+
+
+# ------------------------------------------------------------------ conveniences
+
+def encode(x, delta=False, start=0, stream=None):
+    """Encode a device int32 tensor (uint32 bit patterns).  Returns the stream as a uint8 tensor
+    of exact size (this reads the size back, so it synchronises the stream)."""
+    import torch
+    n = x.numel()
+    out = torch.empty(max(1, svb_max_compressed_bytes(n)), dtype=torch.uint8, device=x.device)
+    size = torch.zeros(1, dtype=torch.int64, device=x.device)
+    if delta:
+        svb_delta_encode(n, x, out, start, size, stream)
+    else:
+        svb_encode(n, x, out, size, stream)
+    return out[: int(size.item())]
+
+
+def decode(s, n, delta=False, start=0, out=None, stream=None, check=True):
+    """Decode ``n`` integers from a device uint8 tensor.  Returns an int32 tensor.  With
+    ``check`` the corruption flag is read back (a synchronisation) and raises SvbError."""
+    import torch
+    if out is None:
+        out = torch.empty(max(1, n), dtype=torch.int32, device=s.device)
+    err = torch.zeros(1, dtype=torch.int32, device=s.device) if check else None
+    if delta:
+        svb_delta_decode(n, s, s.numel(), out, start, err, stream)
+    else:
+        svb_decode(n, s, s.numel(), out, err, stream)
+    if check and int(err.item()) != 0:
+        raise SvbError(-2, "decode")
+    return out[:n]

@@ -1,0 +1,69 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and the
+host-only paths (sizes, strings, argument validation) behave without touching a GPU."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1709_08990_amd as svb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w \*]*?\b(svb_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_codec():
+    names = declared_functions()
+    for required in ("svb_encode", "svb_decode", "svb_delta_encode", "svb_delta_decode",
+                     "svb_encode_batch", "svb_decode_batch", "svb_control_bytes",
+                     "svb_max_compressed_bytes", "svb_strerror", "svb_release_workspace"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(svb.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_python_binding_mirrors_the_abi():
+    for name in declared_functions():
+        assert hasattr(svb, name), name
+
+
+def test_sizes():
+    assert svb.svb_control_bytes(0) == 0
+    assert svb.svb_control_bytes(1) == 1
+    assert svb.svb_control_bytes(4) == 1
+    assert svb.svb_control_bytes(5) == 2
+    assert svb.svb_max_compressed_bytes(5) == 2 + 20
+    assert svb.svb_max_compressed_bytes(1 << 28) == (1 << 26) + (1 << 30)
+
+
+def test_strings():
+    assert svb.svb_strerror(0) == "ok"
+    assert "corrupt" in svb.svb_strerror(-2)
+    assert svb.svb_version().startswith("svb-gfx950")
+
+
+def test_argument_errors_are_synchronous():
+    """These return before any HIP call, so they run on a machine without a GPU."""
+    L = svb.lib()
+    assert L.svb_decode(5, None, 10, None, None, None) == -1          # null pointers
+    assert L.svb_decode(9, 4096, 2, 4096, None, None) == -1           # in_bytes < ceil(n/4)
+    assert L.svb_decode(8, 4096, 64, 4098, None, None) == -1          # misaligned uint32 out
+    assert L.svb_decode(1 << 41, 4096, 1 << 50, 4096, None, None) == -1  # n too large
+    assert L.svb_encode(4, 4098, 4096, None, None) == -1              # misaligned uint32 in
+    assert L.svb_encode(4, 4096, 4096, 4100, None) == -1              # misaligned out_bytes
+    assert L.svb_encode(0, None, None, None, None) == 0               # n = 0, nothing to write
+    assert L.svb_decode(0, None, 0, None, None, None) == 0
+    assert L.svb_copy_u32(4, 4098, 4096, None) == -1
