@@ -9,62 +9,112 @@
 namespace svb {
 namespace {
 
-// Scratch owned by the library for one (device, stream): the tile ticket and
-// finish counters and the per-tile status words of the look-back scans.
+// Scratch owned by the library for one (device, stream): the per-class tile
+// ticket counters and the per-tile status words of the look-back scans.
 struct Workspace {
-    uint32_t *counters = nullptr;  // 16 words
-    uint64_t *flags = nullptr;     // 2 * cap words: byte prefixes, then value prefixes
-    uint64_t cap = 0;              // tiles
+    uint32_t *counters = nullptr;             // kTicketClasses * kCounterStride words
+    uint32_t base[kTicketClasses] = {};       // counter values after the last launch
+    uint64_t *flags = nullptr;                // encoder look-back: cap status words
+    uint64_t cap = 0;                         // status words
     uint32_t epoch = 0;
+    uint8_t *scratch = nullptr;               // decoder offsets and sums
+    uint64_t scratch_bytes = 0;
 };
 
 std::mutex g_mu;
 std::map<std::pair<int, uintptr_t>, Workspace> g_ws;
 
 constexpr uint32_t kEpochLimit = 1u << 20;  // status words carry a 20-bit epoch
+constexpr uint64_t kFlagWordsPerTile = 1;  // the encoder's byte-offset word
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SVB_OK : SVB_ERR_HIP; }
 
 // Workspace for the calling thread's device and `s`, with room for `tiles`
-// tiles, and a fresh epoch for one launch.
-int acquire(hipStream_t s, uint64_t tiles, Workspace **out, uint32_t *epoch) {
+// tiles, and a fresh epoch for one launch.  Caller holds g_mu.
+int acquire_locked(hipStream_t s, uint64_t tiles, Workspace **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
-    std::lock_guard<std::mutex> lock(g_mu);
     Workspace &w = g_ws[std::make_pair(dev, (uintptr_t)s)];
     if (!w.counters) {
-        if (hipMalloc((void **)&w.counters, 16 * sizeof(uint32_t)) != hipSuccess) {
+        const uint64_t words = (uint64_t)kTicketClasses * kCounterStride;
+        if (hipMalloc((void **)&w.counters, words * sizeof(uint32_t)) != hipSuccess) {
             w.counters = nullptr;
             return SVB_ERR_NOMEM;
         }
-        if (launch_fill(w.counters, 16, 0u, s) != hipSuccess) return SVB_ERR_HIP;
+        if (launch_fill(w.counters, words, 0u, s) != hipSuccess) return SVB_ERR_HIP;
+        for (uint32_t c = 0; c < kTicketClasses; ++c) w.base[c] = 0;
     }
-    if (tiles > w.cap) {
+    // status words of consecutive tiles sit kFlagStride words apart
+    const uint64_t words = tiles * kFlagStride;
+    if (words > w.cap) {
         uint64_t cap = 1024;
-        while (cap < tiles) cap <<= 1;
+        while (cap < words) cap <<= 1;
         if (w.flags) {
             if (hipStreamSynchronize(s) != hipSuccess) return SVB_ERR_HIP;
             (void)hipFree(w.flags);
             w.flags = nullptr;
             w.cap = 0;
         }
-        if (hipMalloc((void **)&w.flags, 2 * cap * sizeof(uint64_t)) != hipSuccess) {
+        if (hipMalloc((void **)&w.flags, kFlagWordsPerTile * cap * sizeof(uint64_t)) != hipSuccess) {
             w.flags = nullptr;
             return SVB_ERR_NOMEM;
         }
-        if (launch_fill((uint32_t *)w.flags, 4 * cap, 0u, s) != hipSuccess) return SVB_ERR_HIP;
+        if (launch_fill((uint32_t *)w.flags, 2 * kFlagWordsPerTile * cap, 0u, s) != hipSuccess) return SVB_ERR_HIP;
         w.cap = cap;
         w.epoch = 0;
     }
     w.epoch += 1;
     if (w.epoch >= kEpochLimit) {
         // every epoch value has been used: clear the words and start over
-        if (launch_fill((uint32_t *)w.flags, 4 * w.cap, 0u, s) != hipSuccess) return SVB_ERR_HIP;
+        if (launch_fill((uint32_t *)w.flags, 2 * kFlagWordsPerTile * w.cap, 0u, s) != hipSuccess)
+            return SVB_ERR_HIP;
         w.epoch = 1;
     }
     *out = &w;
-    *epoch = w.epoch;
     return SVB_OK;
+}
+
+uint64_t *byte_flags(const Workspace &w) { return w.flags; }
+
+// At least `bytes` of decoder scratch (contents undefined).  Caller holds g_mu.
+int ensure_scratch(Workspace &w, uint64_t bytes, hipStream_t s) {
+    if (bytes <= w.scratch_bytes) return SVB_OK;
+    uint64_t cap = 1ull << 16;
+    while (cap < bytes) cap <<= 1;
+    if (w.scratch) {
+        if (hipStreamSynchronize(s) != hipSuccess) return SVB_ERR_HIP;
+        (void)hipFree(w.scratch);
+        w.scratch = nullptr;
+        w.scratch_bytes = 0;
+    }
+    if (hipMalloc((void **)&w.scratch, cap) != hipSuccess) {
+        w.scratch = nullptr;
+        return SVB_ERR_NOMEM;
+    }
+    w.scratch_bytes = cap;
+    return SVB_OK;
+}
+
+// Tile queue for one launch of `grid` workgroups over `tiles` tiles.
+TileQueue make_queue(const Workspace &w, uint32_t tiles, uint32_t grid) {
+    TileQueue q;
+    q.counters = w.counters;
+    for (uint32_t c = 0; c < kTicketClasses; ++c) q.base[c] = w.base[c];
+    q.classes = grid < kTicketClasses ? grid : kTicketClasses;
+    q.num_tiles = tiles;
+    return q;
+}
+
+// After a launch: the class's tiles were taken once each, and every workgroup
+// of the class also took `past_end` tickets beyond the last tile (1 for a
+// kernel that asks for one tile at a time, 2 for the decoder, which asks two
+// tiles ahead).
+void advance_queue(Workspace &w, const TileQueue &q, uint32_t grid, uint32_t past_end) {
+    for (uint32_t c = 0; c < q.classes; ++c) {
+        const uint32_t tiles_c = (q.num_tiles - c + q.classes - 1) / q.classes;
+        const uint32_t wgs_c = (grid - c + q.classes - 1) / q.classes;
+        w.base[c] += tiles_c + past_end * wgs_c;
+    }
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
@@ -82,20 +132,24 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
     if (out_bytes && !aligned8(out_bytes)) return SVB_ERR_INVALID;
     if (n == 0) return zero_u64(out_bytes, s);
     if (!in || !out || !aligned4(in)) return SVB_ERR_INVALID;
-    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    const uint32_t tiles = (uint32_t)((n + kTileInts - 1) / kTileInts);
+    const uint32_t grid = encode_grid(delta, tiles);
+    std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
-    EncodeArgs a;
-    int st = acquire(s, tiles, &w, &a.epoch);
+    int st = acquire_locked(s, tiles, &w);
     if (st != SVB_OK) return st;
+    EncodeArgs a;
     a.in = in;
     a.n = n;
     a.out = out;
     a.start = start;
     a.out_bytes = out_bytes;
-    a.counters = w->counters;
-    a.byte_flags = w->flags;
-    a.num_tiles = (uint32_t)tiles;
-    return hip_status(launch_encode(a, delta, s));
+    a.q = make_queue(*w, tiles, grid);
+    a.byte_flags = byte_flags(*w);
+    a.epoch = w->epoch;
+    st = hip_status(launch_encode(a, delta, grid, s));
+    if (st == SVB_OK) advance_queue(*w, a.q, grid, kEncodeTicketsPastEnd);
+    return st;
 }
 
 int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
@@ -106,27 +160,71 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     if (n == 0) return SVB_OK;
     if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
     if (in_bytes < (n + 3) / 4) return SVB_ERR_INVALID;
-    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    const uint32_t tiles = (uint32_t)((n + kTileInts - 1) / kTileInts);
+    const uint64_t sub_ints = kTileInts / kSubsPerTile;
+    const uint64_t subs = (n + sub_ints - 1) / sub_ints;
+    const uint64_t supers = (n + kSuperInts - 1) / kSuperInts;
+    // scratch: sub_loc | sub_vloc (u32 per sub-tile), sup_bytes (u32) and
+    // sup_off (u64) per super-tile, tile_sum | tile_vpre (u32 per tile)
+    auto up8 = [](uint64_t b) { return (b + 7) & ~7ull; };
+    const uint64_t o_sub_loc = 0;
+    const uint64_t o_sub_vloc = o_sub_loc + up8(4 * subs);
+    const uint64_t o_sup_bytes = o_sub_vloc + up8(4 * subs);
+    const uint64_t o_sup_off = o_sup_bytes + up8(4 * supers);
+    const uint64_t o_tile_sum = o_sup_off + 8 * supers;
+    const uint64_t o_tile_vpre = o_tile_sum + up8(4ull * tiles);
+    const uint64_t need = o_tile_vpre + up8(4ull * tiles);
+    const uint32_t grid = decode_grid(delta ? 1 : 0, tiles);
+    std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
-    DecodeArgs a;
-    int st = acquire(s, tiles, &w, &a.epoch);
+    int st = acquire_locked(s, 1, &w);
     if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+
+    // 1-2: byte offset of every sub-tile from the control stream
+    ReduceArgs ra;
+    ra.in = in;
+    ra.in_bytes = in_bytes;
+    ra.n = n;
+    ra.sub_loc = (uint32_t *)(sc + o_sub_loc);
+    ra.sup_bytes = (uint32_t *)(sc + o_sup_bytes);
+    ra.num_subs = subs;
+    ra.num_supers = supers;
+    if ((st = hip_status(launch_control_reduce(ra, s))) != SVB_OK) return st;
+    if ((st = hip_status(launch_scan(ra.sup_bytes, sc + o_sup_off, supers, true, s))) != SVB_OK) return st;
+
+    DecodeArgs a;
     a.in = in;
     a.in_bytes = in_bytes;
     a.n = n;
     a.out = out;
     a.start = start;
     a.err = err;
-    a.counters = w->counters;
-    a.byte_flags = w->flags;
-    a.val_flags = w->flags + w->cap;
-    a.num_tiles = (uint32_t)tiles;
-    return hip_status(launch_decode(a, delta, s));
+    a.sub_loc = ra.sub_loc;
+    a.sup_off = (const uint64_t *)(sc + o_sup_off);
+    a.sub_vloc = (uint32_t *)(sc + o_sub_vloc);
+    a.tile_sum = (uint32_t *)(sc + o_tile_sum);
+    a.tile_vpre = (const uint32_t *)(sc + o_tile_vpre);
+    a.num_subs = subs;
+    if (delta) {
+        // 3-4: value sum of every tile, and their exclusive prefix
+        const uint32_t sgrid = decode_grid(2, tiles);
+        a.q = make_queue(*w, tiles, sgrid);
+        if ((st = hip_status(launch_decode(a, 2, sgrid, s))) != SVB_OK) return st;
+        advance_queue(*w, a.q, sgrid, kDecodeTicketsPastEnd);
+        if ((st = hip_status(launch_scan(a.tile_sum, sc + o_tile_vpre, tiles, false, s))) != SVB_OK) return st;
+    }
+    // 5: decode
+    a.q = make_queue(*w, tiles, grid);
+    st = hip_status(launch_decode(a, delta ? 1 : 0, grid, s));
+    if (st == SVB_OK) advance_queue(*w, a.q, grid, kDecodeTicketsPastEnd);
+    return st;
 }
 
 }  // namespace
 
-uint32_t persistent_grid(const void *kernel, uint32_t num_tiles) {
+uint32_t persistent_grid(const void *kernel, uint32_t num_tiles, uint32_t block_threads) {
     static std::mutex mu;
     static std::map<std::pair<int, const void *>, uint32_t> cache;
     int dev = 0;
@@ -141,7 +239,7 @@ uint32_t persistent_grid(const void *kernel, uint32_t num_tiles) {
             int cus = 0, per_cu = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
                 cus = 256;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWorkgroupThreads, 0) != hipSuccess ||
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block_threads, 0) != hipSuccess ||
                 per_cu <= 0)
                 per_cu = 4;
             grid = (uint32_t)(cus * per_cu);
@@ -200,6 +298,7 @@ void svb_release_workspace(void) {
         (void)hipDeviceSynchronize();
         if (kv.second.counters) (void)hipFree(kv.second.counters);
         if (kv.second.flags) (void)hipFree(kv.second.flags);
+        if (kv.second.scratch) (void)hipFree(kv.second.scratch);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);

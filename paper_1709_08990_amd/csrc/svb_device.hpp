@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "svb_internal.hpp"
+
 namespace svb {
 
 // 16-byte vector whose only alignment requirement is 4 bytes: global
@@ -85,33 +87,40 @@ __device__ __forceinline__ uint64_t flag_word(uint32_t epoch, uint32_t status, u
 template <int VB>
 __device__ __forceinline__ void flag_publish(uint64_t *flags, uint32_t tile, uint32_t epoch,
                                              uint32_t status, uint64_t value) {
-    __hip_atomic_store(flags + tile, flag_word<VB>(epoch, status, value), __ATOMIC_RELAXED,
+    __hip_atomic_store(flags + (uint64_t)tile * kFlagStride, flag_word<VB>(epoch, status, value), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of tile `tile` from the words of tiles 0..tile-1.  Called by
-// one full wave.  Tiles were handed out in increasing order by an atomic ticket,
-// so every predecessor belongs to a workgroup that is already running and will
-// publish: the wait always ends.  Sums are modulo 2^VB (VB = 32 for delta values).
+// Exclusive prefix of tile `tile` from the words of tiles 0..tile-1, run by
+// one full wave.  The tile's own aggregate is published right after the first
+// window of predecessor words has been requested, so the wave never waits for
+// its own store before reading.  Tiles of one ticket class are handed out in
+// increasing order to running workgroups, so every predecessor is held by a
+// workgroup that makes progress: the wait always ends.  Sums are modulo 2^VB.
+// The caller publishes the inclusive prefix (excl + total) when it suits it.
 template <int VB>
-__device__ uint64_t lookback(const uint64_t *flags, uint32_t tile, uint32_t epoch) {
+__device__ uint64_t lookback(uint64_t *flags, uint32_t tile, uint32_t epoch, uint64_t total) {
     const uint32_t lane = lane_id();
     const uint64_t vmask = (1ull << VB) - 1ull;
+    if (tile == 0) return 0;
     uint64_t excl = 0;
     int64_t pos = (int64_t)tile - 1;
-    while (pos >= 0) {
+    bool published = false;
+    for (;;) {
         const int64_t idx = pos - (int64_t)lane;
         for (;;) {
-            uint32_t st;
-            uint64_t val;
-            if (idx >= 0) {
-                const uint64_t w = __hip_atomic_load(flags + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st = ((uint32_t)(w >> (VB + 2)) == epoch) ? (uint32_t)((w >> VB) & 3u) : 0u;
-                val = w & vmask;
-            } else {
-                st = kInclusive;  // before tile 0: an inclusive prefix of zero
-                val = 0;
+            uint64_t w = 0;
+            if (idx >= 0) w = __hip_atomic_load(flags + idx * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!published) {
+                if (lane == 0) flag_publish<VB>(flags, tile, epoch, kAggregate, total);
+                published = true;
             }
+            uint32_t st;
+            if (idx >= 0)
+                st = ((uint32_t)(w >> (VB + 2)) == epoch) ? (uint32_t)((w >> VB) & 3u) : 0u;
+            else
+                st = kInclusive;  // before tile 0: an inclusive prefix of zero
+            const uint64_t val = (idx >= 0) ? (w & vmask) : 0ull;
             const uint64_t invalid = __ballot(st == 0);
             const uint64_t incl = __ballot(st == kInclusive);
             const uint64_t first = incl & (~incl + 1ull);           // nearest inclusive lane
@@ -127,35 +136,50 @@ __device__ uint64_t lookback(const uint64_t *flags, uint32_t tile, uint32_t epoc
         }
         pos -= kWave;
     }
-    return excl;
 }
 
 // ---------------------------------------------------------------- byte windows
 
 // The 16 bytes at in[a .. a+16) as four little-endian dwords, reading only
 // [a, limit) (bytes at or past limit read as 0).  `in` has any alignment.
-__device__ __forceinline__ void load_window16(const uint8_t *in, uint64_t a, uint64_t limit,
-                                              uint32_t &d0, uint32_t &d1, uint32_t &d2, uint32_t &d3) {
-    const uintptr_t addr = (uintptr_t)in + a;
-    const uintptr_t base = addr & ~(uintptr_t)3;
-    const uint32_t sh = (uint32_t)(addr & 3);
-    const uintptr_t end = (uintptr_t)in + limit;
-    if (base + 20 <= end && base >= (uintptr_t)in) {
-        const u32x4 w = *(const u32x4 *)base;
-        const uint32_t w4 = *(const uint32_t *)(base + 16);
-        d0 = __builtin_amdgcn_alignbyte(w.y, w.x, sh);
-        d1 = __builtin_amdgcn_alignbyte(w.z, w.y, sh);
-        d2 = __builtin_amdgcn_alignbyte(w.w, w.z, sh);
-        d3 = __builtin_amdgcn_alignbyte(w4, w.w, sh);
-    } else {
-        uint32_t d[4] = {0u, 0u, 0u, 0u};
+// Used for the first and last tiles of a stream, where a 20-byte window
+// could leave the buffer.
+__device__ __forceinline__ void load_window16_checked(const uint8_t *in, uint64_t a, uint64_t limit,
+                                                      uint32_t &d0, uint32_t &d1, uint32_t &d2, uint32_t &d3) {
+    uint32_t d[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const uint32_t byte = (a + i < limit) ? (uint32_t)in[a + i] : 0u;
-            d[i >> 2] |= byte << (8 * (i & 3));
-        }
-        d0 = d[0]; d1 = d[1]; d2 = d[2]; d3 = d[3];
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t byte = (a + i < limit) ? (uint32_t)in[a + i] : 0u;
+        d[i >> 2] |= byte << (8 * (i & 3));
     }
+    d0 = d[0]; d1 = d[1]; d2 = d[2]; d3 = d[3];
+}
+
+// Raw 20-byte window around in[a]: the dword-aligned dwords covering
+// [a, a + 16), plus the byte shift of a inside the first one.  The caller
+// guarantees the window lies inside the buffer.
+struct Window {
+    u32x4 w;
+    uint32_t w4;
+    uint32_t sh;
+};
+
+__device__ __forceinline__ Window load_window(const uint8_t *in, uint64_t a) {
+    const uint8_t *pa = in + a;
+    Window r;
+    r.sh = (uint32_t)((uintptr_t)pa & 3u);
+    const uint8_t *base = pa - r.sh;
+    r.w = *(const u32x4 *)base;
+    r.w4 = *(const uint32_t *)(base + 16);
+    return r;
+}
+
+__device__ __forceinline__ void align_window(const Window &r, uint32_t &d0, uint32_t &d1, uint32_t &d2,
+                                             uint32_t &d3) {
+    d0 = __builtin_amdgcn_alignbyte(r.w.y, r.w.x, r.sh);
+    d1 = __builtin_amdgcn_alignbyte(r.w.z, r.w.y, r.sh);
+    d2 = __builtin_amdgcn_alignbyte(r.w.w, r.w.z, r.sh);
+    d3 = __builtin_amdgcn_alignbyte(r.w4, r.w.w, r.sh);
 }
 
 // Select word q (0..3) of (d0,d1,d2,d3) without dynamic register indexing.

@@ -52,20 +52,29 @@ def stress_lengths(n=1 << 28, seed=3, chunk=1 << 24):
     out = np.empty(n, dtype=np.uint32)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        lens = rng.choice(4, size=e - s, p=[0.4, 0.3, 0.2, 0.1]) + 1
+        u = rng.random(e - s)
+        lens = 1 + (u >= 0.4).astype(np.int64) + (u >= 0.7) + (u >= 0.9)
         out[s:e] = _values_for_lengths(rng, lens)
     return out
 
 
-def docid_gaps(n=1 << 26, seed=2):
+def docid_gaps(n=1 << 26, seed=2, chunk=1 << 24):
     """Gaps between sorted document ids: Geometric(p=1/8) on {1,2,...} with probability 0.99,
-    uniform in [2^8, 2^20) with probability 0.01."""
+    uniform in [2^8, 2^20) with probability 0.01.  The geometric draw is the inverse CDF,
+    ceil(log(U) / log(1 - p)) for U uniform in (0, 1]."""
     rng = np.random.default_rng(seed)
-    small = rng.geometric(1.0 / 8.0, size=n).astype(np.uint64)
-    big = rng.integers(1 << 8, 1 << 20, size=n, dtype=np.uint64)
-    pick_big = rng.random(n) < 0.01
-    g = np.where(pick_big, big, small)
-    return np.minimum(g, np.uint64(MASK32)).astype(np.uint32)
+    out = np.empty(n, dtype=np.uint32)
+    scale = 1.0 / np.log1p(-1.0 / 8.0)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        u = 1.0 - rng.random(e - s)                  # (0, 1]
+        g = np.ceil(np.log(u) * scale)
+        g = np.maximum(g, 1.0).astype(np.uint32)
+        big = rng.random(e - s) < 0.01
+        nb = int(big.sum())
+        g[big] = rng.integers(1 << 8, 1 << 20, size=nb, dtype=np.uint32)
+        out[s:e] = g
+    return out
 
 
 def docids(n=1 << 26, seed=2, start=0):
