@@ -1,21 +1,33 @@
 #!/usr/bin/env python3
 """Stream VByte on one MI355X: delta-decode throughput against the HBM roofline.
 
-One step = one delta decode (svb_delta_decode: control-byte lengths, byte-offset
-scan, byte gather, fused wrap-around prefix sum, store) of 2^26 sorted document
-ids whose gaps are geometric with mean 8 (probability 0.99) or uniform in
+One step = one svb_delta_decode call (control-byte lengths -> group byte
+offsets -> group value sums -> running-sum decode) of 2^26 sorted document ids
+whose gaps are geometric with mean 8 (probability 0.99) or uniform in
 [2^8, 2^20) (probability 0.01), start value 0.  The compressed input is made by
-the library's own delta encoder and is resident in HBM before timing starts.
+the library's delta encoder and is resident in HBM before timing starts.
 
 Prints one JSON line.  Besides the headline it carries:
-  roofline      the decode kernel's algorithmic bytes per launch over its average
-                duration (HIP events on the launch stream) against 8 TB/s;
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average duration (HIP events recorded by the library on the
+                launch stream, over a second pass of the timed steps) against
+                8 TB/s, and the HBM bytes per launch from committed rocprofv3
+                counters;
+  kernels       average duration of every kernel of the call;
   cpu_baseline  the scalar C oracle, single-threaded, on the host cores;
-  encode        delta encode of the same array, timed the same way;
-  flushed       the decode kernel with a 1 GiB cache-evicting write before each launch;
-  at_2p28       delta decode (and encode) of the same generator at 2^28 integers.
+  encode        delta encode of the same array;
+  flushed       the whole call with a 1 GiB cache-evicting write before each;
+  copy          a plain copy kernel (the practical bandwidth ceiling);
+  at_2p28       delta decode of the same generator at 2^28 integers, and plain
+                decode of 2^28 integers with unpredictable lengths.
+
+`python bench.py --summarize-counters FETCH.csv WRITE.csv OUT.md` turns two
+rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) into the
+counter summary that later runs read back (no GPU needed for that step).
 """
 import argparse
+import collections
+import csv
 import glob
 import hashlib
 import json
@@ -32,6 +44,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "decoded uint32/s + achieved HBM GB/s (% of peak), delta decode, 1 GPU"
 WORKLOAD = ("delta decode of 2^26 sorted uint32 document ids: gaps Geometric(1/8) on {1,2,...} "
             "w.p. 0.99, uniform in [2^8, 2^20) w.p. 0.01, running sum wrapping mod 2^32, start 0")
+N_HEAD = 1 << 26
+COPY_WORDS = 1 << 26                     # 256 MiB copied by the ceiling / counter-scaling copy
+COUNTERS_FILE = "counters_decode_delta_docids_2p26.md"
+DOMINANT_SYMBOL = "decode_kernel<1>"     # rocprofv3 name fragment of the delta decode pass
+COPY_SYMBOL = "copy_kernel"
 
 
 def log(msg):
@@ -47,10 +64,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(name):
-    """HBM bytes per launch from a committed counter summary, if it was taken on the current
-    kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", name)
+def stored_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", COUNTERS_FILE)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -73,9 +90,75 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def time_launches(fn, steps, torch, before=None):
-    """Runs fn() `steps` times on the current stream with an event pair around each launch.
-    Returns (wall seconds for the whole loop, mean per-launch milliseconds)."""
+# ------------------------------------------------------------------ counters (offline)
+
+def _counter_means(path, counter):
+    """Mean value per dispatch of `counter` for every kernel name in a rocprofv3 counter CSV."""
+    per = collections.defaultdict(list)
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def _pick(means, fragment):
+    hits = [(k, v) for k, v in means.items() if fragment in k]
+    if not hits:
+        raise SystemExit("no kernel matching %r in counter file" % fragment)
+    return hits[0]
+
+
+def summarize_counters(fetch_csv, write_csv, out_md, command):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the dominant kernel, each scaled by what
+    the same counter reads for the copy kernel, which moves exactly COPY_WORDS * 4 bytes each way."""
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    copy_bytes = 4.0 * COPY_WORDS
+    kf, f_dom = _pick(fetch, DOMINANT_SYMBOL)
+    _, f_copy = _pick(fetch, COPY_SYMBOL)
+    kw, w_dom = _pick(write, DOMINANT_SYMBOL)
+    _, w_copy = _pick(write, COPY_SYMBOL)
+    f_scale = copy_bytes / (f_copy * 1024.0)
+    w_scale = copy_bytes / (w_copy * 1024.0)
+    fetched = f_dom * 1024.0 * f_scale
+    written = w_dom * 1024.0 * w_scale
+    lines = [
+        "# HBM traffic of the delta decode pass, docids 2^26",
+        "",
+        "Two rocprofv3 counter passes over bench.py (one counter each):",
+        "",
+        "    " + command.replace("{COUNTER}", "FETCH_SIZE"),
+        "    " + command.replace("{COUNTER}", "WRITE_SIZE"),
+        "",
+        "Counters are KiB per dispatch, averaged over dispatches.  Each is scaled by",
+        "bytes / counter of the copy kernel in the same run, which reads and writes",
+        "exactly %d bytes." % copy_bytes,
+        "",
+        "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---|---|---|",
+        "| %s | %.1f | %.1f |" % (kf, f_dom, w_dom),
+        "| copy (%d B each way) | %.1f | %.1f |" % (copy_bytes, f_copy, w_copy),
+        "",
+        "fetch_scale: %.4f" % f_scale,
+        "write_scale: %.4f" % w_scale,
+        "fetched_bytes_per_launch: %.0f" % fetched,
+        "written_bytes_per_launch: %.0f" % written,
+        "traffic_bytes_per_launch: %.0f" % (fetched + written),
+        "source_digest: %s" % source_digest(),
+        "",
+    ]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+# ------------------------------------------------------------------ GPU measurement
+
+def event_loop(fn, steps, torch, before=None):
+    """Runs fn() `steps` times with a torch event pair around each call on the current stream.
+    Returns (wall seconds, mean per-call milliseconds)."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -87,8 +170,110 @@ def time_launches(fn, steps, torch, before=None):
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
-    return wall, ms
+    return wall, sum(a.elapsed_time(b) for a, b in ev) / steps
+
+
+def kernel_means(svb):
+    """Average milliseconds per kernel name from the library's event records."""
+    per = collections.defaultdict(list)
+    for name, ms in svb.svb_kernel_times():
+        per[name].append(ms)
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def timed_steps(svb, torch, fn, steps, warmup):
+    """`warmup` untimed calls, then the timed region: `steps` calls between two device
+    synchronisations (wall clock; whole-job throughput), then the same `steps` calls again with
+    the library recording HIP events around each kernel on the launch stream (per-kernel
+    durations; the event records add a few microseconds per kernel, which is why the wall-clock
+    region runs without them).  Returns (wall seconds, per-kernel mean ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    svb.svb_kernel_times()  # drop stale records
+    svb.svb_set_kernel_timing(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    svb.svb_set_kernel_timing(False)
+    return wall, kernel_means(svb)
+
+
+def gbs(nbytes, ms):
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def measure_delta(svb, torch, x_dev, steps, warmup, flush_buf=None):
+    n = x_dev.numel()
+    comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(n, x_dev, comp, 0, size)
+    torch.cuda.synchronize()
+    nbytes = int(size.item())
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    alg = nbytes + 4 * n
+
+    def dec():
+        svb.svb_delta_decode(n, comp, nbytes, out, 0, err)
+
+    wall, kms = timed_steps(svb, torch, dec, steps, warmup)
+    ok = bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+    call_ms = 1e3 * wall / steps
+    res = {"n": n, "compressed_bytes": nbytes, "bits_per_int": 8.0 * nbytes / n, "alg_bytes_per_call": alg,
+           "wall_s": wall, "ms_per_call": call_ms, "round_trip_ok": ok,
+           "uint32_per_s": n / (call_ms * 1e-3), "call_GBps": gbs(alg, call_ms),
+           "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS, "kernels_ms": kms}
+    if flush_buf is not None:
+        fl = lambda: svb.svb_fill_u32(flush_buf.numel(), flush_buf, 0)
+        _, fms = event_loop(dec, max(3, steps // 2), torch, before=fl)
+        res["flushed"] = {"ms_per_call": fms, "GBps": gbs(alg, fms), "frac_of_peak": gbs(alg, fms) / HBM_PEAK_GBS,
+                          "note": "1 GiB fill before each call evicts L2 and the 256 MB MALL"}
+
+    def enc():
+        svb.svb_delta_encode(n, x_dev, comp, 0, size)
+
+    ewall, ekms = timed_steps(svb, torch, enc, steps, max(1, warmup // 2))
+    ems = 1e3 * ewall / steps
+    res["encode"] = {"ms_per_call": ems, "uint32_per_s": n / (ems * 1e-3), "GBps": gbs(alg, ems),
+                     "frac_of_peak": gbs(alg, ems) / HBM_PEAK_GBS, "kernels_ms": ekms,
+                     "size_ok": int(size.item()) == nbytes}
+    del comp, out
+    return res
+
+
+def measure_plain(svb, torch, x_dev, steps, warmup):
+    n = x_dev.numel()
+    comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_encode(n, x_dev, comp, size)
+    torch.cuda.synchronize()
+    nbytes = int(size.item())
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    alg = nbytes + 4 * n
+    wall, kms = timed_steps(svb, torch, lambda: svb.svb_decode(n, comp, nbytes, out), steps, warmup)
+    ok = bool(torch.equal(out, x_dev))
+    call_ms = 1e3 * wall / steps
+    del comp, out
+    return {"n": n, "compressed_bytes": nbytes, "ms_per_call": call_ms, "uint32_per_s": n / (call_ms * 1e-3),
+            "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
+            "kernels_ms": kms, "round_trip_ok": ok}
+
+
+def measure_copy(svb, torch, steps):
+    a = torch.empty(COPY_WORDS, dtype=torch.int32, device="cuda").fill_(7)
+    b = torch.empty_like(a)
+    svb.svb_copy_u32(COPY_WORDS, a, b)
+    _, ms = event_loop(lambda: svb.svb_copy_u32(COPY_WORDS, a, b), steps, torch)
+    ok = bool(torch.equal(a, b))
+    del a, b
+    return {"bytes_each_way": 4 * COPY_WORDS, "ms": ms, "GBps": gbs(8 * COPY_WORDS, ms),
+            "frac_of_peak": gbs(8 * COPY_WORDS, ms) / HBM_PEAK_GBS, "ok": ok}
 
 
 def run_cpu_baseline(x, min_seconds=10.0):
@@ -99,7 +284,7 @@ def run_cpu_baseline(x, min_seconds=10.0):
     t_end = time.perf_counter() + min_seconds
     while len(times) < 3 or time.perf_counter() < t_end:
         t0 = time.perf_counter()
-        vals, _ = oracle.decode(stream, x.size, delta=True, start=0)
+        oracle.decode(stream, x.size, delta=True, start=0)
         times.append(time.perf_counter() - t0)
         if len(times) >= 200:
             break
@@ -107,51 +292,9 @@ def run_cpu_baseline(x, min_seconds=10.0):
     med = times[len(times) // 2]
     model, ncpu = host_cpu()
     return {"value": x.size / med, "unit": "uint32/s", "cores": 1, "kind": "oracle",
-            "sample": "full %d-integer delta decode, %d repetitions (median), host memory" % (x.size, len(times)),
+            "sample": "full %d-integer delta decode (the bench workload), %d repetitions, median, host memory"
+                      % (x.size, len(times)),
             "host_cpu": model, "host_threads_available": ncpu}
-
-
-def measure_decode(svb, torch, n, x_dev, steps, warmup, flush_buf=None):
-    """Encode once on the GPU, then time delta decodes.  Returns a dict of results."""
-    comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
-    size = torch.zeros(1, dtype=torch.int64, device="cuda")
-    svb.svb_delta_encode(n, x_dev, comp, 0, size)
-    torch.cuda.synchronize()
-    nbytes = int(size.item())
-    out = torch.empty(n, dtype=torch.int32, device="cuda")
-    err = torch.zeros(1, dtype=torch.int32, device="cuda")
-
-    def dec():
-        svb.svb_delta_decode(n, comp, nbytes, out, 0, err)
-
-    def enc():
-        svb.svb_delta_encode(n, x_dev, comp, 0, size)
-
-    for _ in range(warmup):
-        dec()
-    wall, ms = time_launches(dec, steps, torch)
-    torch.cuda.synchronize()
-    ok = bool(torch.equal(out, x_dev)) and int(err.item()) == 0
-    alg = nbytes + 4 * n
-    res = {"n": n, "compressed_bytes": nbytes, "bits_per_int": 8.0 * nbytes / n,
-           "alg_bytes_per_launch": alg, "wall_s": wall, "kernel_ms": ms, "round_trip_ok": ok,
-           "decode_uint32_per_s": n / (ms * 1e-3), "decode_GBps": alg / (ms * 1e-3) / 1e9}
-    res["decode_frac_of_peak"] = res["decode_GBps"] / HBM_PEAK_GBS
-    if flush_buf is not None:
-        fl = lambda: svb.svb_fill_u32(flush_buf.numel(), flush_buf, 0)
-        _, fms = time_launches(dec, max(3, steps // 2), torch, before=fl)
-        res["flushed"] = {"kernel_ms": fms, "GBps": alg / (fms * 1e-3) / 1e9,
-                          "frac_of_peak": alg / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                          "note": "1 GiB fill before each launch evicts L2 and the 256 MB MALL"}
-    for _ in range(max(1, warmup // 2)):
-        enc()
-    _, ems = time_launches(enc, steps, torch)
-    torch.cuda.synchronize()
-    res["encode"] = {"kernel_ms": ems, "uint32_per_s": n / (ems * 1e-3),
-                     "GBps": alg / (ems * 1e-3) / 1e9, "frac_of_peak": alg / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "size_ok": int(size.item()) == nbytes}
-    del comp, out
-    return res
 
 
 def main():
@@ -160,8 +303,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurement")
+    ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurements")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
+    ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} -- python3 bench.py "
+                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, command=args.counter_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
@@ -175,38 +324,44 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     svb.lib()
-    n = 1 << 26
-    log("generating %d document ids" % n)
-    x, _ = inputs.docids(n, seed=2)
+    log("generating %d document ids" % N_HEAD)
+    x, _ = inputs.docids(N_HEAD, seed=2)
     x_dev = torch.from_numpy(x.view(np.int32)).cuda()
     flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
-    log("timing delta decode, %d warmup + %d steps" % (args.warmup, args.steps))
-    r = measure_decode(svb, torch, n, x_dev, args.steps, args.warmup, flush_buf=flush)
+    log("delta decode: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    r = measure_delta(svb, torch, x_dev, args.steps, args.warmup, flush_buf=flush)
     assert r["round_trip_ok"], "delta decode did not reproduce the input"
-    log("decode %.4f ms/launch, %.1f GB/s" % (r["kernel_ms"], r["decode_GBps"]))
+    dom_name = max(r["kernels_ms"], key=r["kernels_ms"].get)
+    dom_ms = r["kernels_ms"][dom_name]
+    log("delta decode %.4f ms/call; dominant kernel %s %.4f ms" % (r["ms_per_call"], dom_name, dom_ms))
+    copy = measure_copy(svb, torch, max(5, args.steps // 2))
+    log("copy %.1f GB/s" % copy["GBps"])
 
-    traffic = stored_traffic("counters_delta_decode_docids_2p26.md")
     line = {
         "metric": METRIC,
-        "value": n * args.steps / r["wall_s"],
+        "value": r["uint32_per_s"],
         "unit": "uint32/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * r["wall_s"] / args.steps,
+        "ms_per_step": r["ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": n, "compressed_bytes": r["compressed_bytes"],
+        "config": {"workload": WORKLOAD, "n": N_HEAD, "compressed_bytes": r["compressed_bytes"],
                    "bits_per_int": round(r["bits_per_int"], 4), "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "hbm", "achieved": r["decode_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["decode_frac_of_peak"], "traffic": traffic,
-                     "kernel": "svb::decode_kernel<4, true>", "kernel_ms": r["kernel_ms"],
-                     "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
+        "roofline": {"bound": "hbm", "achieved": gbs(r["alg_bytes_per_call"], dom_ms), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs(r["alg_bytes_per_call"], dom_ms) / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(), "kernel": dom_name, "kernel_ms": dom_ms,
+                     "alg_bytes_per_launch": r["alg_bytes_per_call"],
+                     "whole_call": {"ms": r["ms_per_call"], "GBps": r["call_GBps"],
+                                    "frac": r["call_frac_of_peak"]}},
+        "kernels_ms": r["kernels_ms"],
         "flushed": r.get("flushed"),
         "encode": r["encode"],
+        "copy": copy,
     }
     del x_dev
     if not args.no_2p28:
@@ -215,12 +370,22 @@ def main():
         x2, _ = inputs.docids(n2, seed=2)
         x2_dev = torch.from_numpy(x2.view(np.int32)).cuda()
         del x2
-        r2 = measure_decode(svb, torch, n2, x2_dev, max(5, args.steps // 2), 2, flush_buf=flush)
+        r2 = measure_delta(svb, torch, x2_dev, max(5, args.steps // 2), 2, flush_buf=flush)
         assert r2["round_trip_ok"], "2^28 delta decode did not reproduce the input"
-        line["at_2p28"] = {k: r2[k] for k in ("n", "compressed_bytes", "kernel_ms", "decode_uint32_per_s",
-                                               "decode_GBps", "decode_frac_of_peak", "flushed", "encode")}
-        log("2^28 decode %.4f ms/launch, %.1f GB/s" % (r2["kernel_ms"], r2["decode_GBps"]))
         del x2_dev
+        log("2^28 delta decode %.4f ms/call (%.1f%% of peak)" % (r2["ms_per_call"], 100 * r2["call_frac_of_peak"]))
+        line["at_2p28"] = {"delta_docids": {k: r2[k] for k in (
+            "n", "compressed_bytes", "ms_per_call", "uint32_per_s", "call_GBps", "call_frac_of_peak", "kernels_ms",
+            "flushed", "encode")}}
+        log("generating %d stress integers" % n2)
+        x3 = inputs.stress_lengths(n2, seed=3)
+        x3_dev = torch.from_numpy(x3.view(np.int32)).cuda()
+        del x3
+        r3 = measure_plain(svb, torch, x3_dev, max(5, args.steps // 2), 2)
+        assert r3["round_trip_ok"], "2^28 plain decode did not reproduce the input"
+        del x3_dev
+        log("2^28 plain decode %.4f ms/call (%.1f%% of peak)" % (r3["ms_per_call"], 100 * r3["call_frac_of_peak"]))
+        line["at_2p28"]["plain_stress"] = r3
     del flush
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

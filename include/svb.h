@@ -30,9 +30,11 @@
  *  - Calls on different streams may run concurrently: the library keeps a
  *    separate scratch workspace per (device, stream).  Calls on one stream
  *    are ordered by the stream.
- *  - The only library-owned memory is that scratch workspace (a few counters
- *    and one 8-byte status word per tile of 4096 integers; grown on demand,
- *    freed by svb_release_workspace).
+ *  - The only library-owned memory is that scratch workspace: eight ticket
+ *    counters, one 8-byte status word per encoder tile of 4096 integers, and
+ *    20 bytes per decoder group of 8192 integers (byte total, byte offset,
+ *    value sum, value prefix); grown on demand, freed by
+ *    svb_release_workspace.
  *  - Return value: SVB_OK (0) or a negative svb_status.  The library never
  *    aborts the process.
  */
@@ -57,6 +59,14 @@ enum svb_status {
 /* Value a decode kernel writes to the caller's device `err` word when the
  * control bytes describe more data than in_bytes holds. */
 #define SVB_DECODE_CORRUPT 1u
+
+/* Value the delta decoder writes to `err` if a workgroup waited about a
+ * second for the running sum of the data before it (never expected: every
+ * earlier piece is owned by a running workgroup; this turns a wait that
+ * cannot end into an error instead of a hung device).  The output is then
+ * incomplete.  The encoders report the same condition by writing
+ * UINT64_MAX to out_bytes. */
+#define SVB_DECODE_STALLED 2u
 
 /* Largest n accepted by the single-stream calls (2^40 integers). */
 #define SVB_MAX_N (((uint64_t)1) << 40)
@@ -153,6 +163,20 @@ const char *svb_strerror(int status);
 /* Frees every scratch workspace the library holds (all devices and streams).
  * Synchronises the devices first.  Later calls allocate again. */
 void svb_release_workspace(void);
+
+/*
+ * Per-kernel timing (measurement aid).  svb_set_kernel_timing(1) makes every
+ * later codec call record a pair of HIP events on its stream around each
+ * kernel it launches; 0 turns recording off.  svb_kernel_times reads the
+ * records of the calling thread made since its previous call, oldest first:
+ * it synchronises on them, writes up to `cap` kernel names (static strings)
+ * and durations in milliseconds, forgets all of them, and returns how many
+ * there were (or a negative svb_status).  Kernel names: "group_bytes",
+ * "scan_offsets", "group_sums", "scan_sums", "decode", "decode_delta",
+ * "encode", "encode_delta".
+ */
+int svb_set_kernel_timing(int enable);
+int svb_kernel_times(const char **names, float *ms, int cap);
 
 /* Library version string. */
 const char *svb_version(void);

@@ -15,11 +15,12 @@ __all__ = [
     "SvbError", "lib", "svb_control_bytes", "svb_max_compressed_bytes", "svb_encode",
     "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_encode_batch", "svb_decode_batch",
     "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
-    "encode", "decode", "LIB_PATH",
+    "svb_set_kernel_timing", "svb_kernel_times", "encode", "decode", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
+SVB_DECODE_STALLED = 2
 
 _lib = None
 
@@ -53,6 +54,8 @@ def lib():
             "svb_version": (ctypes.c_char_p, []),
             "svb_copy_u32": (i32, [u64, vp, vp, vp]),
             "svb_fill_u32": (i32, [u64, vp, u32, vp]),
+            "svb_set_kernel_timing": (i32, [i32]),
+            "svb_kernel_times": (i32, [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), i32]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -155,6 +158,21 @@ def svb_copy_u32(n, inp, out, stream=None):
 def svb_fill_u32(n, out, value, stream=None):
     return _check(lib().svb_fill_u32(int(n), _ptr(out), int(value) & 0xFFFFFFFF, _stream(stream)),
                   "svb_fill_u32")
+
+
+def svb_set_kernel_timing(enable):
+    return _check(lib().svb_set_kernel_timing(1 if enable else 0), "svb_set_kernel_timing")
+
+
+def svb_kernel_times(cap=4096):
+    """[(kernel name, milliseconds)] recorded by the calling thread since the previous call
+    (synchronises on them; records beyond ``cap`` are dropped)."""
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_float * cap)()
+    n = lib().svb_kernel_times(names, ms, cap)
+    if n < 0:
+        raise SvbError(n, "svb_kernel_times")
+    return [(names[i].decode(), float(ms[i])) for i in range(min(n, cap))]
 
 
 # ------------------------------------------------------------------ conveniences

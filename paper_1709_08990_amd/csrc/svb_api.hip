@@ -1,6 +1,7 @@
 // C ABI of libsvb.so (declared in include/svb.h): argument checks, per-stream
 // scratch workspaces and kernel launches.  No codec arithmetic happens here.
 #include <map>
+#include <vector>
 #include <mutex>
 #include <utility>
 
@@ -28,6 +29,37 @@ constexpr uint32_t kEpochLimit = 1u << 20;  // status words carry a 20-bit epoch
 constexpr uint64_t kFlagWordsPerTile = 1;  // the encoder's byte-offset word
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SVB_OK : SVB_ERR_HIP; }
+
+// Optional per-kernel timing (svb_set_kernel_timing): each codec kernel launch
+// of the calling thread is bracketed by a pair of HIP events recorded on the
+// launch stream; svb_kernel_times reads and forgets the recorded pairs.
+struct KernelTiming {
+    const char *name;
+    hipEvent_t begin, end;
+};
+bool g_timing = false;
+thread_local std::vector<KernelTiming> t_timings;     // recorded, not read yet
+thread_local std::vector<KernelTiming> t_event_pool;  // events ready for reuse
+
+// Runs launch() bracketed by events when timing is on.
+template <class F>
+hipError_t timed(const char *name, hipStream_t s, F launch) {
+    if (!g_timing) return launch();
+    KernelTiming k;
+    if (!t_event_pool.empty()) {
+        k = t_event_pool.back();
+        t_event_pool.pop_back();
+    } else {
+        if (hipEventCreate(&k.begin) != hipSuccess) return hipErrorOutOfMemory;
+        if (hipEventCreate(&k.end) != hipSuccess) return hipErrorOutOfMemory;
+    }
+    k.name = name;
+    hipError_t e = hipEventRecord(k.begin, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(k.end, s);
+    t_timings.push_back(k);
+    return e;
+}
 
 // Workspace for the calling thread's device and `s`, with room for `tiles`
 // tiles, and a fresh epoch for one launch.  Caller holds g_mu.
@@ -125,6 +157,32 @@ int zero_u64(uint64_t *p, hipStream_t s) {
     return hip_status(launch_fill((uint32_t *)p, 2, 0u, s));
 }
 
+// Kernels that wait for other workgroups of the same launch (the look-back
+// kernels) are never run concurrently with each other on one device: each is
+// ordered after the previous one, whatever its stream.  Two such launches
+// sharing the device could otherwise each hold the compute units the other's
+// pending workgroups need.  Caller holds g_mu.
+std::map<int, hipEvent_t> g_lookback_done;
+
+int order_lookback_launch(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
+    auto it = g_lookback_done.find(dev);
+    if (it == g_lookback_done.end()) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SVB_ERR_HIP;
+        g_lookback_done[dev] = e;
+        return SVB_OK;
+    }
+    return hip_status(hipStreamWaitEvent(s, it->second, 0));
+}
+
+int lookback_launched(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
+    return hip_status(hipEventRecord(g_lookback_done[dev], s));
+}
+
 int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint64_t *out_bytes,
               bool delta, void *stream) {
     hipStream_t s = (hipStream_t)stream;
@@ -147,9 +205,12 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
     a.q = make_queue(*w, tiles, grid);
     a.byte_flags = byte_flags(*w);
     a.epoch = w->epoch;
-    st = hip_status(launch_encode(a, delta, grid, s));
-    if (st == SVB_OK) advance_queue(*w, a.q, grid, kEncodeTicketsPastEnd);
-    return st;
+    if ((st = order_lookback_launch(s)) != SVB_OK) return st;
+    if ((st = hip_status(timed(delta ? "encode_delta" : "encode", s, [&] { return launch_encode(a, delta, grid, s); }))) !=
+        SVB_OK)
+        return st;
+    advance_queue(*w, a.q, grid, kEncodeTicketsPastEnd);
+    return lookback_launched(s);
 }
 
 int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
@@ -160,21 +221,15 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     if (n == 0) return SVB_OK;
     if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
     if (in_bytes < (n + 3) / 4) return SVB_ERR_INVALID;
-    const uint32_t tiles = (uint32_t)((n + kTileInts - 1) / kTileInts);
-    const uint64_t sub_ints = kTileInts / kSubsPerTile;
-    const uint64_t subs = (n + sub_ints - 1) / sub_ints;
-    const uint64_t supers = (n + kSuperInts - 1) / kSuperInts;
-    // scratch: sub_loc | sub_vloc (u32 per sub-tile), sup_bytes (u32) and
-    // sup_off (u64) per super-tile, tile_sum | tile_vpre (u32 per tile)
-    auto up8 = [](uint64_t b) { return (b + 7) & ~7ull; };
-    const uint64_t o_sub_loc = 0;
-    const uint64_t o_sub_vloc = o_sub_loc + up8(4 * subs);
-    const uint64_t o_sup_bytes = o_sub_vloc + up8(4 * subs);
-    const uint64_t o_sup_off = o_sup_bytes + up8(4 * supers);
-    const uint64_t o_tile_sum = o_sup_off + 8 * supers;
-    const uint64_t o_tile_vpre = o_tile_sum + up8(4ull * tiles);
-    const uint64_t need = o_tile_vpre + up8(4ull * tiles);
-    const uint32_t grid = decode_grid(delta ? 1 : 0, tiles);
+    const uint64_t groups = (n + kGroupInts - 1) / kGroupInts;
+    // scratch: per group data bytes (u32), data offset (u64), value sum (u32),
+    // value prefix (u32)
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_gbytes = 0;
+    const uint64_t o_goff = o_gbytes + up16(4 * groups);
+    const uint64_t o_gvsum = o_goff + up16(8 * groups);
+    const uint64_t o_gvpre = o_gvsum + up16(4 * groups);
+    const uint64_t need = o_gvpre + up16(4 * groups);
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
     int st = acquire_locked(s, 1, &w);
@@ -182,44 +237,38 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
     uint8_t *sc = w->scratch;
 
-    // 1-2: byte offset of every sub-tile from the control stream
-    ReduceArgs ra;
-    ra.in = in;
-    ra.in_bytes = in_bytes;
-    ra.n = n;
-    ra.sub_loc = (uint32_t *)(sc + o_sub_loc);
-    ra.sup_bytes = (uint32_t *)(sc + o_sup_bytes);
-    ra.num_subs = subs;
-    ra.num_supers = supers;
-    if ((st = hip_status(launch_control_reduce(ra, s))) != SVB_OK) return st;
-    if ((st = hip_status(launch_scan(ra.sup_bytes, sc + o_sup_off, supers, true, s))) != SVB_OK) return st;
+    // data-stream offset of every group (and segment), from the control stream
+    GroupBytesArgs ga;
+    ga.in = in;
+    ga.in_bytes = in_bytes;
+    ga.n = n;
+    ga.groups = groups;
+    ga.gbytes = (uint32_t *)(sc + o_gbytes);
+    ga.seg_loc = nullptr;
+    if ((st = hip_status(timed("group_bytes", s, [&] { return launch_group_bytes(ga, s); }))) != SVB_OK) return st;
+    if ((st = hip_status(timed("scan_offsets", s, [&] { return launch_scan(ga.gbytes, sc + o_goff, groups, true, 0u, s); }))) !=
+        SVB_OK)
+        return st;
 
-    DecodeArgs a;
+    DecodeArgs a = {};
     a.in = in;
     a.in_bytes = in_bytes;
     a.n = n;
     a.out = out;
-    a.start = start;
     a.err = err;
-    a.sub_loc = ra.sub_loc;
-    a.sup_off = (const uint64_t *)(sc + o_sup_off);
-    a.sub_vloc = (uint32_t *)(sc + o_sub_vloc);
-    a.tile_sum = (uint32_t *)(sc + o_tile_sum);
-    a.tile_vpre = (const uint32_t *)(sc + o_tile_vpre);
-    a.num_subs = subs;
+    a.groups = groups;
+    a.goff = (const uint64_t *)(sc + o_goff);
+    a.gvsum = (uint32_t *)(sc + o_gvsum);
+    a.gvpre = (const uint32_t *)(sc + o_gvpre);
     if (delta) {
-        // 3-4: value sum of every tile, and their exclusive prefix
-        const uint32_t sgrid = decode_grid(2, tiles);
-        a.q = make_queue(*w, tiles, sgrid);
-        if ((st = hip_status(launch_decode(a, 2, sgrid, s))) != SVB_OK) return st;
-        advance_queue(*w, a.q, sgrid, kDecodeTicketsPastEnd);
-        if ((st = hip_status(launch_scan(a.tile_sum, sc + o_tile_vpre, tiles, false, s))) != SVB_OK) return st;
+        // value sum of every group, then start + their exclusive prefix
+        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s); }))) != SVB_OK) return st;
+        if ((st = hip_status(timed("scan_sums", s, [&] {
+                 return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s);
+             }))) != SVB_OK)
+            return st;
     }
-    // 5: decode
-    a.q = make_queue(*w, tiles, grid);
-    st = hip_status(launch_decode(a, delta ? 1 : 0, grid, s));
-    if (st == SVB_OK) advance_queue(*w, a.q, grid, kDecodeTicketsPastEnd);
-    return st;
+    return hip_status(timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s); }));
 }
 
 }  // namespace
@@ -301,7 +350,37 @@ void svb_release_workspace(void) {
         if (kv.second.scratch) (void)hipFree(kv.second.scratch);
     }
     g_ws.clear();
+    for (auto &kv : g_lookback_done) {
+        (void)hipSetDevice(kv.first);
+        (void)hipEventDestroy(kv.second);
+    }
+    g_lookback_done.clear();
     (void)hipSetDevice(cur);
+}
+
+int svb_set_kernel_timing(int enable) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timing = enable != 0;
+    return SVB_OK;
+}
+
+int svb_kernel_times(const char **names, float *ms, int cap) {
+    if (cap < 0 || (cap > 0 && (!names || !ms))) return SVB_ERR_INVALID;
+    const int n = (int)t_timings.size();
+    int st = n;
+    for (int i = 0; i < n; ++i) {
+        const KernelTiming &k = t_timings[i];
+        if (i < cap && st >= 0) {
+            float t = 0.f;
+            if (hipEventSynchronize(k.end) != hipSuccess || hipEventElapsedTime(&t, k.begin, k.end) != hipSuccess)
+                st = SVB_ERR_HIP;
+            names[i] = k.name;
+            ms[i] = t;
+        }
+        t_event_pool.push_back(k);
+    }
+    t_timings.clear();
+    return st;
 }
 
 const char *svb_version(void) { return "svb-gfx950 0.1.0"; }

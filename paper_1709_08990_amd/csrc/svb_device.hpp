@@ -1,10 +1,9 @@
 // Device-side building blocks shared by the Stream VByte kernels (gfx950, wave64).
 //
 //  - wave-level inclusive scans with DPP row shifts and row broadcasts,
-//  - a decoupled look-back over per-tile 64-bit status words (the serial
-//    "advance the data pointer by C" chain of the paper's decoder, Section 4,
-//    becomes an exclusive scan over tiles),
-//  - byte-window loads that never touch memory outside the stream.
+//  - a decoupled look-back over per-tile 64-bit status words (the encoder's
+//    serial "append after the previous integer's bytes" becomes an exclusive
+//    scan over tiles).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,9 +63,15 @@ __device__ __forceinline__ uint32_t byte_length(uint32_t v) {
     return ((31u - (uint32_t)__builtin_clz(v | 1u)) >> 3) + 1u;
 }
 
-// Low L bytes of v (L in 1..4).
-__device__ __forceinline__ uint32_t low_bytes(uint32_t v, uint32_t L) {
-    return v & (0xFFFFFFFFu >> (32u - 8u * L));
+// ---------------------------------------------------------------- tickets
+
+// Next tile for this workgroup (>= q.num_tiles once its class has none left).
+// Each class's tiles are handed out in increasing order to running workgroups,
+// so a tile's predecessors are always held by workgroups that make progress.
+__device__ __forceinline__ uint32_t take_tile(const TileQueue &q) {
+    const uint32_t cls = blockIdx.x % q.classes;
+    const uint32_t j = atomicAdd(q.counters + cls * kCounterStride, 1u) - q.base[cls];
+    return j * q.classes + cls;
 }
 
 // ---------------------------------------------------------------- look-back
@@ -91,131 +96,96 @@ __device__ __forceinline__ void flag_publish(uint64_t *flags, uint32_t tile, uin
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Polls of predecessor words before a look-back gives up (each poll is a
+// round trip to memory plus a short sleep, about a microsecond): a safety net
+// that turns a wait that cannot end into a reported error instead of a hung
+// device.  Every predecessor is held by a running workgroup, so in normal
+// operation the limit is never reached.
+constexpr uint32_t kLookbackPollLimit = 1u << 22;
+
+// Predecessor words each lane reads per poll: one poll covers
+// kLookbackPerLane * 64 predecessors.  Each poll is a device-coherent read
+// that bypasses the per-XCD L2, and many waves poll at once, so a wider window
+// costs more than it saves (measured on MI355X: 4 or 16 words per lane made a
+// look-back-bound kernel 2.4x and 10x slower than 1).
+#ifndef SVB_LOOKBACK_PER_LANE
+#define SVB_LOOKBACK_PER_LANE 1
+#endif
+constexpr uint32_t kLookbackPerLane = SVB_LOOKBACK_PER_LANE;
+
 // Exclusive prefix of tile `tile` from the words of tiles 0..tile-1, run by
 // one full wave.  The tile's own aggregate is published right after the first
 // window of predecessor words has been requested, so the wave never waits for
-// its own store before reading.  Tiles of one ticket class are handed out in
-// increasing order to running workgroups, so every predecessor is held by a
-// workgroup that makes progress: the wait always ends.  Sums are modulo 2^VB.
-// The caller publishes the inclusive prefix (excl + total) when it suits it.
+// its own store before reading.  Tiles are handed out in increasing order to
+// running workgroups, so every predecessor is held by a workgroup that makes
+// progress: the wait always ends.  Sums are modulo 2^VB.  The caller publishes
+// the inclusive prefix (excl + total) when it suits it.  `stalled` is set (and
+// 0 returned) when the poll limit is reached.
 template <int VB>
-__device__ uint64_t lookback(uint64_t *flags, uint32_t tile, uint32_t epoch, uint64_t total) {
+__device__ uint64_t lookback(uint64_t *flags, uint32_t tile, uint32_t epoch, uint64_t total, bool &stalled) {
+    constexpr uint32_t P = kLookbackPerLane;
     const uint32_t lane = lane_id();
     const uint64_t vmask = (1ull << VB) - 1ull;
+    stalled = false;
     if (tile == 0) return 0;
     uint64_t excl = 0;
-    int64_t pos = (int64_t)tile - 1;
+    int64_t pos = (int64_t)tile - 1;  // nearest predecessor not summed yet
     bool published = false;
+    uint32_t polls = 0;
     for (;;) {
-        const int64_t idx = pos - (int64_t)lane;
+        // lane l covers predecessors pos - P l - j, j = 0..P-1 (nearest first)
         for (;;) {
-            uint64_t w = 0;
-            if (idx >= 0) w = __hip_atomic_load(flags + idx * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t w[P];
+#pragma unroll
+            for (uint32_t j = 0; j < P; ++j) {
+                const int64_t idx = pos - (int64_t)(P * lane + j);
+                w[j] = idx >= 0 ? __hip_atomic_load(flags + idx * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : 0ull;
+            }
             if (!published) {
                 if (lane == 0) flag_publish<VB>(flags, tile, epoch, kAggregate, total);
                 published = true;
             }
-            uint32_t st;
-            if (idx >= 0)
-                st = ((uint32_t)(w >> (VB + 2)) == epoch) ? (uint32_t)((w >> VB) & 3u) : 0u;
-            else
-                st = kInclusive;  // before tile 0: an inclusive prefix of zero
-            const uint64_t val = (idx >= 0) ? (w & vmask) : 0ull;
-            const uint64_t invalid = __ballot(st == 0);
-            const uint64_t incl = __ballot(st == kInclusive);
-            const uint64_t first = incl & (~incl + 1ull);           // nearest inclusive lane
-            const uint64_t below = incl ? (first - 1ull) : ~0ull;   // lanes that must be aggregates
-            if ((invalid & below) == 0) {
-                const uint64_t take = incl ? (below | first) : ~0ull;
-                const uint64_t mine = ((take >> lane) & 1ull) ? val : 0ull;
+            // per lane: the first inclusive word (fi = P if none) and whether a
+            // word before it has not been published by this launch
+            uint32_t fi = P;
+            bool bad = false;
+#pragma unroll
+            for (uint32_t j = 0; j < P; ++j) {
+                const int64_t idx = pos - (int64_t)(P * lane + j);
+                uint32_t st = kInclusive;  // before tile 0: an inclusive prefix of zero
+                if (idx >= 0) st = ((uint32_t)(w[j] >> (VB + 2)) == epoch) ? (uint32_t)((w[j] >> VB) & 3u) : 0u;
+                if (fi == P) {
+                    if (st == kInclusive)
+                        fi = j;
+                    else if (st == 0)
+                        bad = true;
+                }
+            }
+            const uint64_t has_incl = __ballot(fi < P);
+            const uint64_t first = has_incl & (~has_incl + 1ull);        // nearest lane with an inclusive word
+            const uint64_t before = has_incl ? (first - 1ull) : ~0ull;   // lanes that must be all aggregates
+            if ((__ballot(bad) & (before | first)) == 0) {
+                const bool whole = (before >> lane) & 1ull;
+                const bool part = (first >> lane) & 1ull;
+                uint64_t mine = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < P; ++j) {
+                    const int64_t idx = pos - (int64_t)(P * lane + j);
+                    const uint64_t val = idx >= 0 ? (w[j] & vmask) : 0ull;
+                    if (whole || (part && j <= fi)) mine += val;
+                }
                 excl = (excl + wave_sum_u64(mine)) & vmask;
-                if (incl) return excl;
+                if (has_incl) return excl;
                 break;
+            }
+            if (++polls >= kLookbackPollLimit) {
+                stalled = true;
+                return 0;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        pos -= kWave;
-    }
-}
-
-// ---------------------------------------------------------------- byte windows
-
-// The 16 bytes at in[a .. a+16) as four little-endian dwords, reading only
-// [a, limit) (bytes at or past limit read as 0).  `in` has any alignment.
-// Used for the first and last tiles of a stream, where a 20-byte window
-// could leave the buffer.
-__device__ __forceinline__ void load_window16_checked(const uint8_t *in, uint64_t a, uint64_t limit,
-                                                      uint32_t &d0, uint32_t &d1, uint32_t &d2, uint32_t &d3) {
-    uint32_t d[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const uint32_t byte = (a + i < limit) ? (uint32_t)in[a + i] : 0u;
-        d[i >> 2] |= byte << (8 * (i & 3));
-    }
-    d0 = d[0]; d1 = d[1]; d2 = d[2]; d3 = d[3];
-}
-
-// Raw 20-byte window around in[a]: the dword-aligned dwords covering
-// [a, a + 16), plus the byte shift of a inside the first one.  The caller
-// guarantees the window lies inside the buffer.
-struct Window {
-    u32x4 w;
-    uint32_t w4;
-    uint32_t sh;
-};
-
-__device__ __forceinline__ Window load_window(const uint8_t *in, uint64_t a) {
-    const uint8_t *pa = in + a;
-    Window r;
-    r.sh = (uint32_t)((uintptr_t)pa & 3u);
-    const uint8_t *base = pa - r.sh;
-    r.w = *(const u32x4 *)base;
-    r.w4 = *(const uint32_t *)(base + 16);
-    return r;
-}
-
-__device__ __forceinline__ void align_window(const Window &r, uint32_t &d0, uint32_t &d1, uint32_t &d2,
-                                             uint32_t &d3) {
-    d0 = __builtin_amdgcn_alignbyte(r.w.y, r.w.x, r.sh);
-    d1 = __builtin_amdgcn_alignbyte(r.w.z, r.w.y, r.sh);
-    d2 = __builtin_amdgcn_alignbyte(r.w.w, r.w.z, r.sh);
-    d3 = __builtin_amdgcn_alignbyte(r.w4, r.w.w, r.sh);
-}
-
-// Select word q (0..3) of (d0,d1,d2,d3) without dynamic register indexing.
-__device__ __forceinline__ uint32_t pick4(uint32_t q, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3) {
-    const uint32_t lo = (q & 1u) ? d1 : d0;
-    const uint32_t hi = (q & 1u) ? d3 : d2;
-    return (q & 2u) ? hi : lo;
-}
-
-// The four integers of one block from its 16-byte window (Section 4: the
-// shuffle of Fig. 4 done with byte-align instructions).  c = control byte.
-__device__ __forceinline__ void gather_block(uint32_t c, uint32_t d0, uint32_t d1, uint32_t d2,
-                                             uint32_t d3, uint32_t &v0, uint32_t &v1, uint32_t &v2,
-                                             uint32_t &v3) {
-    const uint32_t L0 = (c & 3u) + 1u;
-    const uint32_t L1 = ((c >> 2) & 3u) + 1u;
-    const uint32_t L2 = ((c >> 4) & 3u) + 1u;
-    const uint32_t L3 = ((c >> 6) & 3u) + 1u;
-    const uint32_t o1 = L0;            // 1..4
-    const uint32_t o2 = o1 + L1;       // 2..8
-    const uint32_t o3 = o2 + L2;       // 3..12
-    v0 = low_bytes(d0, L0);
-    {
-        const uint32_t q = o1 >> 2, s = o1 & 3u;
-        const uint32_t lo = q ? d1 : d0, hi = q ? d2 : d1;
-        v1 = low_bytes(__builtin_amdgcn_alignbyte(hi, lo, s), L1);
-    }
-    {
-        const uint32_t q = o2 >> 2, s = o2 & 3u;
-        const uint32_t lo = pick4(q, d0, d1, d2, d3), hi = pick4(q + 1u, d0, d1, d2, d3);
-        v2 = low_bytes(__builtin_amdgcn_alignbyte(hi, lo, s), L2);
-    }
-    {
-        const uint32_t q = o3 >> 2, s = o3 & 3u;
-        const uint32_t lo = pick4(q, d0, d1, d2, d3), hi = pick4(q + 1u, d0, d1, d2, d3);
-        v3 = low_bytes(__builtin_amdgcn_alignbyte(hi, lo, s), L3);
+        pos -= (int64_t)P * kWave;
     }
 }
 

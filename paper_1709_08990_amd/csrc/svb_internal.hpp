@@ -32,7 +32,6 @@ constexpr uint32_t kCounterStride = 32;  // uint32 words between counters (128 b
 
 // Tickets each workgroup takes beyond the last tile of its class, per kernel.
 constexpr uint32_t kEncodeTicketsPastEnd = 1;
-constexpr uint32_t kDecodeTicketsPastEnd = 3;       // the decoder asks three tiles ahead
 
 struct TileQueue {
     uint32_t *counters;             // kTicketClasses counters, kCounterStride words apart
@@ -41,21 +40,27 @@ struct TileQueue {
     uint32_t num_tiles;
 };
 
-// A decode tile is four sub-tiles (one per data wave) of 64 x K blocks; a
-// super-tile (one workgroup of the control reduction) covers 256 threads x 64
-// blocks = kSubsPerSuper sub-tiles.
-constexpr uint32_t kSubsPerTile = 4;
-constexpr uint32_t kSubsPerSuper = 256 / kBlocksPerThread;
-constexpr uint64_t kSuperInts = 256ull * 64ull * 4ull;
+// Decoding geometry.  A segment is what one wave decodes at a time: 64 lanes x
+// 16 integers, each lane owning four consecutive control bytes.  A group is
+// kGroupSegs consecutive segments, walked in order by one wave; the pre-pass
+// and the scans work per group.
+constexpr uint32_t kSegInts = 1024;
+constexpr uint32_t kSegCtrl = kSegInts / 4;
+#ifndef SVB_GROUP_SEGS
+#define SVB_GROUP_SEGS 8
+#endif
+constexpr uint32_t kGroupSegs = SVB_GROUP_SEGS;
+constexpr uint64_t kGroupInts = (uint64_t)kSegInts * kGroupSegs;
+constexpr uint64_t kGroupCtrl = kGroupInts / 4;
+static_assert(kGroupSegs >= 4 && kGroupSegs <= 64 && (64 % kGroupSegs) == 0, "group of 4..64 segments");
 
-struct ReduceArgs {
+struct GroupBytesArgs {
     const uint8_t *in;     // stream; its first ceil(n/4) bytes are the control stream
     uint64_t in_bytes;
     uint64_t n;
-    uint32_t *sub_loc;     // out: data byte offset of each sub-tile inside its super-tile
-    uint32_t *sup_bytes;   // out: data bytes of each super-tile
-    uint64_t num_subs;
-    uint64_t num_supers;
+    uint64_t groups;
+    uint32_t *gbytes;      // out: data bytes of each group
+    uint32_t *seg_loc;     // out (may be null): byte offset of each segment inside its group
 };
 
 struct DecodeArgs {
@@ -63,15 +68,11 @@ struct DecodeArgs {
     uint64_t in_bytes;
     uint64_t n;
     uint32_t *out;
-    uint32_t start;
     uint32_t *err;
-    TileQueue q;
-    const uint32_t *sub_loc;   // byte offset of each sub-tile inside its super-tile
-    const uint64_t *sup_off;   // data-stream byte offset of each super-tile
-    uint32_t *sub_vloc;        // value offset of each sub-tile inside its tile (written by SUMS)
-    uint32_t *tile_sum;        // value sum of each tile (written by SUMS)
-    const uint32_t *tile_vpre; // exclusive value prefix of each tile (read by DELTA)
-    uint64_t num_subs;
+    uint64_t groups;
+    const uint64_t *goff;  // data-stream byte offset of each group
+    uint32_t *gvsum;       // value sum of each group (written in value-sum mode)
+    const uint32_t *gvpre; // start + exclusive value prefix of each group (read in delta mode)
 };
 
 struct EncodeArgs {
@@ -85,12 +86,15 @@ struct EncodeArgs {
     uint32_t epoch;
 };
 
-// Persistent grid size for the codec kernels over `num_tiles` tiles.
-uint32_t decode_grid(int mode, uint32_t num_tiles);  // mode: 0 plain, 1 delta, 2 value sums
+// Decoding: mode 0 plain, 1 delta (running sum), 2 value sums per group.
+enum DecodeMode { kPlain = 0, kDelta = 1, kSums = 2 };
+hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s);
+// Exclusive prefix sums of m uint32 values: 64-bit (wide) or modulo 2^32 plus `start`.
+hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s);
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s);
+
+// Encoding (persistent, decoupled look-back over tile byte totals).
 uint32_t encode_grid(bool delta, uint32_t num_tiles);
-hipError_t launch_control_reduce(const ReduceArgs &a, hipStream_t s);
-hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, hipStream_t s);
-hipError_t launch_decode(const DecodeArgs &a, int mode, uint32_t grid, hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, bool delta, uint32_t grid, hipStream_t s);
 hipError_t launch_copy(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t s);
 hipError_t launch_fill(uint32_t *out, uint64_t n, uint32_t value, hipStream_t s);
