@@ -68,6 +68,10 @@ enum svb_status {
  * UINT64_MAX to out_bytes. */
 #define SVB_DECODE_STALLED 2u
 
+/* Value a batched decode writes to `err` when the lists hold more integers
+ * than the caller's total_ints bound (nothing is decoded then). */
+#define SVB_BATCH_OVERFLOW 3u
+
 /* Largest n accepted by the single-stream calls (2^40 integers). */
 #define SVB_MAX_N (((uint64_t)1) << 40)
 
@@ -120,13 +124,22 @@ int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t 
                      uint32_t start, uint32_t *err, void *stream);
 
 /*
- * Batched calls: m independent streams in one persistent launch with a
- * device-side work queue.  The lists stand for posting lists (Section 5):
- * many lists of very uneven lengths.  All array arguments are DEVICE arrays
- * of m entries; the host never needs to read them.
+ * Batched calls (Section 5's posting lists: many lists of very uneven
+ * length): m independent lists decoded or encoded by one fixed sequence of
+ * launches whose work list is built on the device.  Each list is cut into
+ * items of a tuned number of 1024-integer segments (one wave each); lists
+ * longer than one item first get per-item byte offsets (and, for delta
+ * decoding, per-item value carries) from a scan.  All array arguments are
+ * DEVICE arrays of m entries; the host never reads them.
+ *
+ * total_ints (host value) is an upper bound on sum(counts[i]); it sizes the
+ * library's scratch (about 24 bytes per item).  If the counts add up to more,
+ * nothing is done: decode sets err to SVB_BATCH_OVERFLOW and encode writes
+ * UINT64_MAX to every out_bytes[i].
  *
  * svb_encode_batch
- *   counts[i]     integers in list i.
+ *   counts[i]     integers in list i (<= SVB_MAX_N; a larger count is
+ *                 skipped and its out_bytes[i] set to UINT64_MAX).
  *   in_off[i]     index (in uint32 units) of list i's first integer in `in`.
  *   out_off[i]    byte offset in `out` where stream i is written; the caller
  *                 reserves svb_max_compressed_bytes(counts[i]) bytes there and
@@ -134,28 +147,50 @@ int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t 
  *   out_bytes[i]  receives stream i's size (may be NULL).
  *   starts        NULL: plain encoding.  Otherwise delta encoding of list i
  *                 from starts[i].
+ * The streams are byte-identical to svb_encode / svb_delta_encode of each list.
  */
 int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
-                     const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes,
-                     const uint32_t *starts, void *stream);
+                     const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes, const uint32_t *starts,
+                     uint64_t total_ints, void *stream);
 
 /*
  * svb_decode_batch
  *   counts[i]     integers in list i.
  *   in_off[i]     byte offset of stream i in `in`.
- *   in_bytes[i]   bytes readable at in + in_off[i] (>= ceil(counts[i]/4)).
+ *   in_bytes[i]   bytes readable at in + in_off[i] (a value below
+ *                 ceil(counts[i]/4) makes list i corrupt: it is skipped).
  *   out_off[i]    index (uint32 units) where list i's integers are written;
  *                 output ranges must not overlap.
  *   starts        NULL: plain decoding.  Otherwise delta decoding of list i
  *                 from starts[i].
  *   err           device uint32 or NULL; set to SVB_DECODE_CORRUPT if any
- *                 stream is corrupt (see svb_decode).
- * The host-side checks cover the pointers only (the arrays live on the
- * device); a short in_bytes[i] is reported through err.
+ *                 stream is corrupt (see svb_decode), SVB_BATCH_OVERFLOW as
+ *                 above.
  */
 int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                      const uint64_t *in_bytes, const uint8_t *in, const uint64_t *out_off,
-                     uint32_t *out, const uint32_t *starts, uint32_t *err, void *stream);
+                     uint32_t *out, const uint32_t *starts, uint64_t total_ints, uint32_t *err,
+                     void *stream);
+
+/*
+ * Autotuning of the batched calls: the item size (1, 2, 4 or 8 segments of
+ * 1024 integers per wave) is chosen per device and per kind of call (decode
+ * or encode, plain or delta).  svb_autotune_decode_batch times each candidate
+ * on the given batch (the arguments of svb_decode_batch; it decodes the batch
+ * several times and synchronises the stream), keeps the fastest for later
+ * calls of that kind on the current device, and writes it to *item_segs.
+ * svb_autotune_encode_batch does the same for encoding.
+ * svb_set_batch_item_segments(kind, segs) sets the choice directly;
+ * kind = 2 * (encode ? 1 : 0) + (delta ? 1 : 0).  The default is 2.
+ */
+int svb_autotune_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
+                              const uint64_t *in_bytes, const uint8_t *in, const uint64_t *out_off,
+                              uint32_t *out, const uint32_t *starts, uint64_t total_ints, uint32_t *err,
+                              uint32_t *item_segs, void *stream);
+int svb_autotune_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
+                              const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes,
+                              const uint32_t *starts, uint64_t total_ints, uint32_t *item_segs, void *stream);
+int svb_set_batch_item_segments(int kind, uint32_t item_segs);
 
 /* Message for a status code (static string). */
 const char *svb_strerror(int status);
@@ -173,7 +208,10 @@ void svb_release_workspace(void);
  * and durations in milliseconds, forgets all of them, and returns how many
  * there were (or a negative svb_status).  Kernel names: "group_bytes",
  * "scan_offsets", "group_sums", "scan_sums", "decode", "decode_delta",
- * "encode", "encode_delta".
+ * "encode", "encode_delta", and for the batched calls "batch_count",
+ * "batch_scan_lists", "batch_map", "batch_item_bytes", "batch_scan_offsets",
+ * "batch_item_sums", "batch_scan_sums", "batch_decode", "batch_encode" (a
+ * scan of more than 65536 values is three kernels under one name).
  */
 int svb_set_kernel_timing(int enable);
 int svb_kernel_times(const char **names, float *ms, int cap);

@@ -15,12 +15,14 @@ __all__ = [
     "SvbError", "lib", "svb_control_bytes", "svb_max_compressed_bytes", "svb_encode",
     "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_encode_batch", "svb_decode_batch",
     "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
-    "svb_set_kernel_timing", "svb_kernel_times", "encode", "decode", "LIB_PATH",
+    "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
+    "svb_set_batch_item_segments", "encode", "decode", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
 SVB_DECODE_STALLED = 2
+SVB_BATCH_OVERFLOW = 3
 
 _lib = None
 
@@ -47,8 +49,11 @@ def lib():
             "svb_delta_encode": (i32, [u64, vp, vp, u32, vp, vp]),
             "svb_decode": (i32, [u64, vp, u64, vp, vp, vp]),
             "svb_delta_decode": (i32, [u64, vp, u64, vp, u32, vp, vp]),
-            "svb_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, vp]),
-            "svb_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "svb_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp]),
+            "svb_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp]),
+            "svb_autotune_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp, vp]),
+            "svb_autotune_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp]),
+            "svb_set_batch_item_segments": (i32, [i32, u32]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -127,16 +132,42 @@ def svb_delta_decode(n, inp, in_bytes, out, start=0, err=None, stream=None):
                   "svb_delta_decode")
 
 
-def svb_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, stream=None):
+def svb_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=0,
+                     stream=None):
     return _check(lib().svb_encode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(inp), _ptr(out_off),
-                                         _ptr(out), _ptr(out_bytes), _ptr(starts), _stream(stream)),
-                  "svb_encode_batch")
+                                         _ptr(out), _ptr(out_bytes), _ptr(starts), int(total_ints),
+                                         _stream(stream)), "svb_encode_batch")
 
 
-def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, err=None, stream=None):
+def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=0, err=None,
+                     stream=None):
     return _check(lib().svb_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
-                                         _ptr(out_off), _ptr(out), _ptr(starts), _ptr(err),
+                                         _ptr(out_off), _ptr(out), _ptr(starts), int(total_ints), _ptr(err),
                                          _stream(stream)), "svb_decode_batch")
+
+
+def svb_autotune_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=0,
+                              err=None, stream=None):
+    """Times each item size on this batch, keeps the fastest for later calls; returns it."""
+    chosen = ctypes.c_uint32(0)
+    _check(lib().svb_autotune_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
+                                           _ptr(out_off), _ptr(out), _ptr(starts), int(total_ints), _ptr(err),
+                                           ctypes.addressof(chosen), _stream(stream)), "svb_autotune_decode_batch")
+    return int(chosen.value)
+
+
+def svb_autotune_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=0,
+                              stream=None):
+    chosen = ctypes.c_uint32(0)
+    _check(lib().svb_autotune_encode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(inp), _ptr(out_off),
+                                           _ptr(out), _ptr(out_bytes), _ptr(starts), int(total_ints),
+                                           ctypes.addressof(chosen), _stream(stream)), "svb_autotune_encode_batch")
+    return int(chosen.value)
+
+
+def svb_set_batch_item_segments(kind, item_segs):
+    """kind = 2 * encode + delta; item_segs in {1, 2, 4, 8}."""
+    return _check(lib().svb_set_batch_item_segments(int(kind), int(item_segs)), "svb_set_batch_item_segments")
 
 
 def svb_strerror(status):

@@ -1,5 +1,6 @@
 // C ABI of libsvb.so (declared in include/svb.h): argument checks, per-stream
 // scratch workspaces and kernel launches.  No codec arithmetic happens here.
+#include <algorithm>
 #include <map>
 #include <vector>
 #include <mutex>
@@ -229,7 +230,8 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     const uint64_t o_goff = o_gbytes + up16(4 * groups);
     const uint64_t o_gvsum = o_goff + up16(8 * groups);
     const uint64_t o_gvpre = o_gvsum + up16(4 * groups);
-    const uint64_t need = o_gvpre + up16(4 * groups);
+    const uint64_t o_scan = o_gvpre + up16(4 * groups);
+    const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
     int st = acquire_locked(s, 1, &w);
@@ -246,7 +248,7 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     ga.gbytes = (uint32_t *)(sc + o_gbytes);
     ga.seg_loc = nullptr;
     if ((st = hip_status(timed("group_bytes", s, [&] { return launch_group_bytes(ga, s); }))) != SVB_OK) return st;
-    if ((st = hip_status(timed("scan_offsets", s, [&] { return launch_scan(ga.gbytes, sc + o_goff, groups, true, 0u, s); }))) !=
+    if ((st = hip_status(timed("scan_offsets", s, [&] { return launch_scan(ga.gbytes, sc + o_goff, groups, true, 0u, s, nullptr, sc + o_scan); }))) !=
         SVB_OK)
         return st;
 
@@ -264,11 +266,164 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
         // value sum of every group, then start + their exclusive prefix
         if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s); }))) != SVB_OK) return st;
         if ((st = hip_status(timed("scan_sums", s, [&] {
-                 return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s);
+                 return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s, nullptr, sc + o_scan);
              }))) != SVB_OK)
             return st;
     }
     return hip_status(timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s); }));
+}
+
+// ---------------------------------------------------------------- batched calls
+
+// Item size (segments per wave) per (device, kind); kind = 2 encode + delta.
+std::map<std::pair<int, int>, uint32_t> g_item_segs;
+constexpr uint32_t kDefaultItemSegs = 2;
+
+bool valid_item_segs(uint32_t g) { return g == 1 || g == 2 || g == 4 || g == 8; }
+
+uint32_t tuned_item_segs(int kind) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_item_segs.find(std::make_pair(dev, kind));
+    return it == g_item_segs.end() ? kDefaultItemSegs : it->second;
+}
+
+struct BatchCall {
+    bool encode;
+    uint32_t m;
+    const uint64_t *counts, *in_off, *in_bytes;
+    const void *in;
+    const uint64_t *out_off;
+    void *out;
+    uint64_t *out_bytes;
+    const uint32_t *starts;
+    uint64_t total_ints;
+    uint32_t *err;
+};
+
+// item_segs = 0: the tuned choice for this kind of call.
+int do_batch(const BatchCall &c, uint32_t item_segs, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (c.m == 0) return SVB_OK;
+    if (!c.counts || !c.in_off || !c.in || !c.out_off || !c.out) return SVB_ERR_INVALID;
+    if (!c.encode && !c.in_bytes) return SVB_ERR_INVALID;
+    if (!aligned8(c.counts) || !aligned8(c.in_off) || !aligned8(c.out_off)) return SVB_ERR_INVALID;
+    if ((c.in_bytes && !aligned8(c.in_bytes)) || (c.out_bytes && !aligned8(c.out_bytes))) return SVB_ERR_INVALID;
+    if ((c.starts && !aligned4(c.starts)) || (c.err && !aligned4(c.err))) return SVB_ERR_INVALID;
+    if (c.encode ? !aligned4(c.in) : !aligned4(c.out)) return SVB_ERR_INVALID;
+    const bool delta = c.starts != nullptr;
+    const int kind = 2 * (c.encode ? 1 : 0) + (delta ? 1 : 0);
+    std::lock_guard<std::mutex> lock(g_mu);
+    const uint32_t G = item_segs ? item_segs : tuned_item_segs(kind);
+    if (!valid_item_segs(G)) return SVB_ERR_INVALID;
+    const uint64_t per_item = (uint64_t)G * kSegInts;
+    const uint64_t t_cap64 = (uint64_t)c.m + (c.total_ints + per_item - 1) / per_item;
+    if (c.total_ints > (1ull << 50) || t_cap64 >= (1ull << 31)) return SVB_ERR_INVALID;
+    const uint64_t T = t_cap64, M = c.m;
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_litems = 0;
+    const uint64_t o_lbase = o_litems + up16(4 * M);
+    const uint64_t o_ilist = o_lbase + up16(4 * (M + 1));
+    const uint64_t o_ibytes = o_ilist + up16(4 * T);
+    const uint64_t o_ioff = o_ibytes + up16(4 * T);
+    const uint64_t o_ivsum = o_ioff + up16(8 * T);
+    const uint64_t o_ivpre = o_ivsum + up16(4 * T);
+    const uint64_t o_scan = o_ivpre + up16(4 * T);
+    const uint64_t scan_bytes = std::max(scan_scratch_bytes(M), scan_scratch_bytes(T));
+    const uint64_t need = o_scan + up16(scan_bytes);
+    Workspace *w;
+    int st = acquire_locked(s, 1, &w);
+    if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    BatchArgs a = {};
+    a.m = c.m;
+    a.counts = c.counts;
+    a.in_off = c.in_off;
+    a.in_bytes = c.encode ? nullptr : c.in_bytes;
+    a.in8 = c.encode ? nullptr : (const uint8_t *)c.in;
+    a.in32 = c.encode ? (const uint32_t *)c.in : nullptr;
+    a.out_off = c.out_off;
+    a.out32 = c.encode ? nullptr : (uint32_t *)c.out;
+    a.out8 = c.encode ? (uint8_t *)c.out : nullptr;
+    a.out_bytes = c.encode ? c.out_bytes : nullptr;
+    a.starts = c.starts;
+    a.err = c.encode ? nullptr : c.err;
+    a.litems = (uint32_t *)(sc + o_litems);
+    a.lbase = (uint32_t *)(sc + o_lbase);
+    a.item_list = (uint32_t *)(sc + o_ilist);
+    a.t_cap = (uint32_t)T;
+    a.ibytes = (uint32_t *)(sc + o_ibytes);
+    a.ioff = (uint64_t *)(sc + o_ioff);
+    a.ivsum = (uint32_t *)(sc + o_ivsum);
+    a.ivpre = (uint32_t *)(sc + o_ivpre);
+    void *scan_scr = sc + o_scan;
+    auto run = [&](const char *name, int phase) {
+        return hip_status(timed(name, s, [&] { return launch_batch(a, G, phase, c.encode, delta, s); }));
+    };
+    if ((st = run("batch_count", kBatchCount)) != SVB_OK) return st;
+    if ((st = hip_status(timed("batch_scan_lists", s, [&] {
+             return launch_scan(a.litems, a.lbase, M, false, 0u, s, a.lbase + M, scan_scr);
+         }))) != SVB_OK)
+        return st;
+    if ((st = run("batch_map", kBatchMap)) != SVB_OK) return st;
+    if ((st = run("batch_item_bytes", kBatchItemBytes)) != SVB_OK) return st;
+    if ((st = hip_status(timed("batch_scan_offsets", s, [&] {
+             return launch_scan(a.ibytes, a.ioff, T, true, 0u, s, nullptr, scan_scr);
+         }))) != SVB_OK)
+        return st;
+    if (!c.encode && delta) {
+        if ((st = run("batch_item_sums", kBatchItemSums)) != SVB_OK) return st;
+        if ((st = hip_status(timed("batch_scan_sums", s, [&] {
+                 return launch_scan(a.ivsum, a.ivpre, T, false, 0u, s, nullptr, scan_scr);
+             }))) != SVB_OK)
+            return st;
+    }
+    return run(c.encode ? "batch_encode" : "batch_decode", kBatchWork);
+}
+
+// Times each item size on the caller's batch and keeps the fastest.
+int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SVB_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SVB_ERR_HIP;
+    }
+    const uint32_t candidates[] = {1, 2, 4, 8};
+    uint32_t best = kDefaultItemSegs;
+    float best_ms = 1e30f;
+    int st = SVB_OK;
+    for (uint32_t g : candidates) {
+        for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_batch(c, g, stream);
+        if (st != SVB_OK) break;
+        float times[3];
+        for (int r = 0; r < 3 && st == SVB_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK) st = do_batch(c, g, stream);
+            if (st == SVB_OK && hipEventRecord(e1, s) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK && hipEventSynchronize(e1) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK && hipEventElapsedTime(&times[r], e0, e1) != hipSuccess) st = SVB_ERR_HIP;
+        }
+        if (st != SVB_OK) break;
+        const float med = std::max(std::min(times[0], times[1]), std::min(std::max(times[0], times[1]), times[2]));
+        if (med < best_ms) {
+            best_ms = med;
+            best = g;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SVB_OK) return st;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_item_segs[std::make_pair(dev, 2 * (c.encode ? 1 : 0) + (c.starts ? 1 : 0))] = best;
+    }
+    if (chosen) *chosen = best;
+    return SVB_OK;
 }
 
 }  // namespace
@@ -325,6 +480,43 @@ int svb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, 
 int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
                      uint32_t *err, void *stream) {
     return do_decode(n, in, in_bytes, out, start, err, true, stream);
+}
+
+int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
+                     const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes, const uint32_t *starts,
+                     uint64_t total_ints, void *stream) {
+    BatchCall c = {true, m, counts, in_off, nullptr, in, out_off, out, out_bytes, starts, total_ints, nullptr};
+    return do_batch(c, 0, stream);
+}
+
+int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                     const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
+                     uint64_t total_ints, uint32_t *err, void *stream) {
+    BatchCall c = {false, m, counts, in_off, in_bytes, in, out_off, out, nullptr, starts, total_ints, err};
+    return do_batch(c, 0, stream);
+}
+
+int svb_autotune_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                              const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
+                              uint64_t total_ints, uint32_t *err, uint32_t *item_segs, void *stream) {
+    BatchCall c = {false, m, counts, in_off, in_bytes, in, out_off, out, nullptr, starts, total_ints, err};
+    return autotune_batch(c, item_segs, stream);
+}
+
+int svb_autotune_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
+                              const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes, const uint32_t *starts,
+                              uint64_t total_ints, uint32_t *item_segs, void *stream) {
+    BatchCall c = {true, m, counts, in_off, nullptr, in, out_off, out, out_bytes, starts, total_ints, nullptr};
+    return autotune_batch(c, item_segs, stream);
+}
+
+int svb_set_batch_item_segments(int kind, uint32_t item_segs) {
+    if (kind < 0 || kind > 3 || !valid_item_segs(item_segs)) return SVB_ERR_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_item_segs[std::make_pair(dev, kind)] = item_segs;
+    return SVB_OK;
 }
 
 const char *svb_strerror(int status) {

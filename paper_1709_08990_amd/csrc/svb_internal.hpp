@@ -89,9 +89,40 @@ struct EncodeArgs {
 // Decoding: mode 0 plain, 1 delta (running sum), 2 value sums per group.
 enum DecodeMode { kPlain = 0, kDelta = 1, kSums = 2 };
 hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s);
-// Exclusive prefix sums of m uint32 values: 64-bit (wide) or modulo 2^32 plus `start`.
-hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s);
+// Exclusive prefix sums of m uint32 values into `out`: 64-bit (wide) or modulo
+// 2^32 plus `start`.  `total` (may be null) receives the sum (u64 when wide,
+// else u32 start + sum).  Above a few tens of thousands of values the scan
+// needs scan_scratch_bytes(m) bytes of device scratch.
+uint64_t scan_scratch_bytes(uint64_t m);
+hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
+                       void *total = nullptr, void *scratch = nullptr);
 hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s);
+
+// Batched calls.  Item = `item_segs` segments of one list = one wave's work.
+struct BatchArgs {
+    uint32_t m;
+    const uint64_t *counts;
+    const uint64_t *in_off;    // decode: byte offset of each stream; encode: uint32 index of each list
+    const uint64_t *in_bytes;  // decode only (null when encoding)
+    const uint8_t *in8;        // decode input
+    const uint32_t *in32;      // encode input
+    const uint64_t *out_off;   // decode: uint32 index of each list; encode: byte offset of each stream
+    uint32_t *out32;           // decode output
+    uint8_t *out8;             // encode output
+    uint64_t *out_bytes;       // encode: stream sizes (may be null)
+    const uint32_t *starts;    // null: plain
+    uint32_t *err;             // decode: corruption / overflow flag (may be null)
+    uint32_t *litems;          // per list: items
+    uint32_t *lbase;           // per list + 1: first item of each list; lbase[m] = items in all
+    uint32_t *item_list;       // per item: its list
+    uint32_t t_cap;            // item capacity of the scratch arrays
+    uint32_t *ibytes;          // per item: data bytes (items that are not the last of their list)
+    uint64_t *ioff;            // per item: exclusive scan of ibytes
+    uint32_t *ivsum;           // per item: sum of stored differences (delta decoding)
+    uint32_t *ivpre;           // per item: exclusive scan of ivsum
+};
+enum BatchPhase { kBatchCount = 0, kBatchMap = 1, kBatchItemBytes = 2, kBatchItemSums = 3, kBatchWork = 4 };
+hipError_t launch_batch(const BatchArgs &a, uint32_t item_segs, int phase, bool encode, bool delta, hipStream_t s);
 
 // Encoding (persistent, decoupled look-back over tile byte totals).
 uint32_t encode_grid(bool delta, uint32_t num_tiles);

@@ -1,0 +1,247 @@
+// Device-wide exclusive prefix sums of uint32 arrays, used by the decoders and
+// the batched calls to turn per-piece byte counts and value sums into offsets
+// and carries (the paper's serial "advance the data pointer" and running sum,
+// Sections 2 and 4, become scans).
+//
+// WIDE: 64-bit sums (byte offsets).  Otherwise sums modulo 2^32 plus `start`
+// (delta carries).  An optional `total` receives the sum of all m values
+// (64-bit, or 32-bit plus start modulo 2^32).
+//
+// Up to kSingleMax values: one workgroup of 1024 threads walks the array in
+// steps of 16384.  Above that: reduce-then-scan over tiles of 16384 values
+// (tile sums, one-workgroup scan of the tile sums, per-tile scan with carry).
+#include <type_traits>
+
+#include "svb_device.hpp"
+#include "svb_internal.hpp"
+
+namespace svb {
+
+namespace {
+
+constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanPer = 16;
+constexpr uint32_t kScanTile = kScanThreads * kScanPer;  // values per workgroup step
+constexpr uint32_t kScanWaves = kScanThreads / kWave;
+constexpr uint64_t kSingleMax = 4ull * kScanTile;
+
+template <bool WIDE>
+using acc_t = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+
+// Inclusive wave scan in the accumulator type.
+__device__ __forceinline__ uint32_t wave_scan_acc(uint32_t x) { return wave_incl_scan(x); }
+__device__ __forceinline__ uint64_t wave_scan_acc(uint64_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Loads the 16 values of thread `tid` in [base, base + kScanTile), 0 past m.
+__device__ __forceinline__ void load16(const uint32_t *in, uint64_t base, uint64_t m, uint32_t tid,
+                                       uint32_t (&x)[kScanPer]) {
+    const uint64_t i0 = base + (uint64_t)tid * kScanPer;
+    if (i0 + kScanPer <= m) {
+#pragma unroll
+        for (uint32_t j = 0; j < kScanPer; j += 4) {
+            const u32x4 w = *(const u32x4 *)(in + i0 + j);
+            x[j] = w.x; x[j + 1] = w.y; x[j + 2] = w.z; x[j + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < kScanPer; ++j) x[j] = (i0 + j < m) ? in[i0 + j] : 0u;
+    }
+}
+
+// Workgroup-wide exclusive prefix of each thread's 16-value sum; returns the
+// thread's prefix and writes the workgroup total to *total (all threads).
+template <typename A>
+__device__ __forceinline__ A block_prefix(A sum, A *s_wtot, A *total) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const A incl = wave_scan_acc(sum);
+    if (lane == kWave - 1) s_wtot[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const A t = lane < kScanWaves ? s_wtot[lane] : (A)0;
+        const A ti = wave_scan_acc(t);
+        if (lane < kScanWaves) s_wtot[lane] = ti - t;
+        if (lane == kWave - 1) s_wtot[kScanWaves] = ti;
+    }
+    __syncthreads();
+    const A pre = s_wtot[wave] + incl - sum;
+    *total = s_wtot[kScanWaves];
+    __syncthreads();
+    return pre;
+}
+
+// Writes thread `tid`'s 16 outputs (exclusive sums, offset by `carry`).
+template <bool WIDE>
+__device__ __forceinline__ void store16(void *out, uint64_t base, uint64_t m, uint32_t tid, acc_t<WIDE> carry,
+                                        const uint32_t (&x)[kScanPer]) {
+    const uint64_t i0 = base + (uint64_t)tid * kScanPer;
+    acc_t<WIDE> y[kScanPer];
+    acc_t<WIDE> run = carry;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; ++j) {
+        y[j] = run;
+        run += x[j];
+    }
+    if (i0 + kScanPer <= m) {
+        if (WIDE) {
+            uint64_t *o = (uint64_t *)out + i0;
+#pragma unroll
+            for (uint32_t j = 0; j < kScanPer; ++j) o[j] = y[j];
+        } else {
+            uint32_t *o = (uint32_t *)out + i0;
+#pragma unroll
+            for (uint32_t j = 0; j < kScanPer; j += 4)
+                *(u32x4 *)(o + j) = u32x4{(uint32_t)y[j], (uint32_t)y[j + 1], (uint32_t)y[j + 2], (uint32_t)y[j + 3]};
+        }
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < kScanPer; ++j) {
+            if (i0 + j < m) {
+                if (WIDE)
+                    ((uint64_t *)out)[i0 + j] = y[j];
+                else
+                    ((uint32_t *)out)[i0 + j] = (uint32_t)y[j];
+            }
+        }
+    }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void write_total(void *total, acc_t<WIDE> v) {
+    if (!total) return;
+    if (WIDE)
+        *(uint64_t *)total = v;
+    else
+        *(uint32_t *)total = (uint32_t)v;
+}
+
+// One workgroup over the whole array.
+template <bool WIDE>
+__global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_t *in, void *out, uint64_t m,
+                                                                   uint32_t start, void *total) {
+    typedef acc_t<WIDE> A;
+    __shared__ A s_wtot[kScanWaves + 1];
+    const uint32_t tid = threadIdx.x;
+    A carry = WIDE ? (A)0 : (A)start;
+    for (uint64_t base = 0; base < m; base += kScanTile) {
+        uint32_t x[kScanPer];
+        load16(in, base, m, tid, x);
+        A sum = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
+        A step_total;
+        const A pre = block_prefix<A>(sum, s_wtot, &step_total);
+        store16<WIDE>(out, base, m, tid, carry + pre, x);
+        carry += step_total;
+    }
+    if (tid == 0) write_total<WIDE>(total, carry);
+}
+
+// Tile t's sum into sums[t] (64-bit for WIDE).
+template <bool WIDE>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t *in, uint64_t m, uint32_t *sums) {
+    typedef acc_t<WIDE> A;
+    __shared__ A s_wtot[kScanWaves + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t x[kScanPer];
+    load16(in, base, m, threadIdx.x, x);
+    A sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
+    A tot;
+    (void)block_prefix<A>(sum, s_wtot, &tot);
+    if (threadIdx.x == 0) {
+        if (WIDE) {
+            // split into two 32-bit words so the tile sums scan as u32 pairs below
+            sums[2 * blockIdx.x] = (uint32_t)tot;
+            sums[2 * blockIdx.x + 1] = (uint32_t)((uint64_t)tot >> 32);
+        } else {
+            sums[blockIdx.x] = (uint32_t)tot;
+        }
+    }
+}
+
+// Exclusive scan of the tile sums by one workgroup (at most a few thousand).
+template <bool WIDE>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_prefix_kernel(const uint32_t *sums, uint64_t tiles,
+                                                                        uint64_t *pre, uint32_t start, void *total) {
+    typedef acc_t<WIDE> A;
+    __shared__ A s_wtot[kScanWaves + 1];
+    const uint32_t tid = threadIdx.x;
+    A carry = WIDE ? (A)0 : (A)start;
+    for (uint64_t base = 0; base < tiles; base += kScanThreads) {
+        const uint64_t t = base + tid;
+        A v = 0;
+        if (t < tiles) v = WIDE ? (A)(sums[2 * t] | ((uint64_t)sums[2 * t + 1] << 32)) : (A)sums[t];
+        A step_total;
+        const A p = block_prefix<A>(v, s_wtot, &step_total);
+        if (t < tiles) pre[t] = (uint64_t)(carry + p);
+        carry += step_total;
+    }
+    if (tid == 0) write_total<WIDE>(total, carry);
+}
+
+// Per-tile scan with the tile's carry.
+template <bool WIDE>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_final_kernel(const uint32_t *in, void *out, uint64_t m,
+                                                                       const uint64_t *pre) {
+    typedef acc_t<WIDE> A;
+    __shared__ A s_wtot[kScanWaves + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t x[kScanPer];
+    load16(in, base, m, threadIdx.x, x);
+    A sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
+    A tot;
+    const A p = block_prefix<A>(sum, s_wtot, &tot);
+    store16<WIDE>(out, base, m, threadIdx.x, (A)pre[blockIdx.x] + p, x);
+}
+
+}  // namespace
+
+uint64_t scan_scratch_bytes(uint64_t m) {
+    if (m <= kSingleMax) return 0;
+    const uint64_t tiles = (m + kScanTile - 1) / kScanTile;
+    return 8 * tiles + 8 * tiles;  // tile sums (two words each when wide), tile prefixes
+}
+
+hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
+                       void *total, void *scratch) {
+    if (m <= kSingleMax) {
+        if (wide)
+            hipLaunchKernelGGL((scan_single_kernel<true>), dim3(1), dim3(kScanThreads), 0, s, in, out, m, start, total);
+        else
+            hipLaunchKernelGGL((scan_single_kernel<false>), dim3(1), dim3(kScanThreads), 0, s, in, out, m, start, total);
+        return hipGetLastError();
+    }
+    if (!scratch) return hipErrorInvalidValue;
+    const uint64_t tiles = (m + kScanTile - 1) / kScanTile;
+    uint32_t *sums = (uint32_t *)scratch;
+    uint64_t *pre = (uint64_t *)((uint8_t *)scratch + 8 * tiles);
+    if (wide) {
+        hipLaunchKernelGGL((scan_tile_sums_kernel<true>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, m, sums);
+        hipLaunchKernelGGL((scan_tile_prefix_kernel<true>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
+                           total);
+        hipLaunchKernelGGL((scan_tile_final_kernel<true>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, out, m,
+                           pre);
+    } else {
+        hipLaunchKernelGGL((scan_tile_sums_kernel<false>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, m, sums);
+        hipLaunchKernelGGL((scan_tile_prefix_kernel<false>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
+                           total);
+        hipLaunchKernelGGL((scan_tile_final_kernel<false>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, out, m,
+                           pre);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace svb

@@ -1,0 +1,435 @@
+// One wave's unit of work for the Stream VByte kernels: a segment of 1024
+// integers (256 control bytes).  Lane l owns control bytes (blocks) l, l + 64,
+// l + 128 and l + 192 of the segment, so each of its four 16-byte store or
+// load instructions covers 1 KiB contiguous.  Shared by the single-stream and
+// the batched kernels; a stream is described by a DecodeArgs (in, in_bytes,
+// n, out).
+#pragma once
+
+#include "svb_device.hpp"
+#include "svb_internal.hpp"
+
+namespace svb {
+
+// Per-wave LDS staging area.  The segment's data bytes start kStagePad bytes
+// in, so that the 8 aligned bytes read around an integer never fall below the
+// area; 16 x 257 bytes of data (the largest 16-byte-aligned span a segment's
+// 4096 data bytes can touch), 16 bytes of over-read for blocks past the end
+// and the 8-byte read window fit below kStageBytes.
+constexpr uint32_t kStagePad = 64;
+constexpr uint32_t kStageBytes = 4224;
+
+__device__ __forceinline__ bool segment_full(const DecodeArgs &p, uint64_t s) { return (s + 1) * kSegInts <= p.n; }
+
+// Integers of block 64 k + lane of segment s (0..4).
+__device__ __forceinline__ uint32_t block_ints(const DecodeArgs &p, uint64_t s, uint32_t k, uint32_t lane) {
+    const uint64_t i0 = s * kSegInts + 4ull * (kWave * k + lane);
+    return i0 < p.n ? (uint32_t)((p.n - i0) < 4 ? (p.n - i0) : 4) : 0u;
+}
+
+// The lane's control bytes of segment s: c[k] is control byte 64 k + lane of
+// the segment, with the codes of integers past n cleared.  Blocks past the end
+// read as 0.
+struct SegCtrl {
+    uint32_t c[4];
+};
+
+__device__ __forceinline__ SegCtrl load_seg_ctrl(const DecodeArgs &p, uint64_t s, uint32_t lane) {
+    const uint8_t *cp = p.in + s * kSegCtrl + lane;
+    SegCtrl r;
+    if (segment_full(p, s)) {
+        // all 256 control bytes lie below ceil(n/4) <= in_bytes
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) r.c[k] = cp[kWave * k];
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t m = block_ints(p, s, k, lane);
+            r.c[k] = m ? (cp[kWave * k] & ((1u << (2 * m)) - 1u)) : 0u;
+        }
+    }
+    return r;
+}
+
+// Per-segment scan state: the lane's control bytes, each of its blocks' byte
+// offset inside the segment's data, and the segment's byte total.
+struct SegPlan {
+    SegCtrl sc;
+    uint32_t off[4];
+    uint32_t total;
+};
+
+__device__ __forceinline__ SegPlan plan_segment(const DecodeArgs &p, uint64_t s, const SegCtrl &sc, uint32_t lane) {
+    SegPlan sp;
+    sp.sc = sc;
+    const bool full = segment_full(p, s);
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t m = full ? 4u : block_ints(p, s, k, lane);
+        const uint32_t nb = m + __builtin_popcount(sc.c[k]) + __builtin_popcount(sc.c[k] & 0xAAu);
+        const uint32_t incl = wave_incl_scan(nb);
+        sp.off[k] = run + incl - nb;
+        run += wave_last(incl);
+    }
+    sp.total = run;
+    return sp;
+}
+
+// A segment's data span in flight: up to 5 x 64 chunks of 16 bytes,
+// [abase, abase + 16 nch), where abase is the span start rounded down to 16.
+// Inside the buffer every chunk is one aligned 16-byte load into registers
+// (lane c takes chunks c, c + 64, ...); at the edges of the buffer the chunks
+// are assembled byte by byte when they are staged, bytes outside
+// [in, in + in_bytes) reading as 0.
+struct Span {
+    const uint8_t *abase;
+    uint32_t nch;
+    bool inside;
+    u32x4a w[5];
+};
+
+__device__ __forceinline__ void span_load(const DecodeArgs &p, Span &sp, uint32_t lane) {
+    sp.inside = sp.abase >= p.in && sp.abase + 16ull * sp.nch <= p.in + p.in_bytes;
+    if (sp.inside) {
+#pragma unroll
+        for (uint32_t i = 0; i < 5; ++i) {
+            const uint32_t c = lane + kWave * i;
+            if (c < sp.nch) sp.w[i] = *(const u32x4a *)(sp.abase + 16 * c);
+        }
+    }
+}
+
+__device__ __forceinline__ void span_to_lds(const DecodeArgs &p, const Span &sp, uint8_t *stage, uint32_t lane) {
+    if (sp.inside) {
+#pragma unroll
+        for (uint32_t i = 0; i < 5; ++i) {
+            const uint32_t c = lane + kWave * i;
+            if (c < sp.nch) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
+        }
+    } else {
+        for (uint32_t c = lane; c < sp.nch; c += kWave) {
+            uint32_t d[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t b = 0; b < 16; ++b) {
+                const uint8_t *a = sp.abase + 16 * c + b;
+                if (a >= p.in && a < p.in + p.in_bytes) d[b >> 2] |= (uint32_t)*a << (8 * (b & 3));
+            }
+            *(u32x4a *)(stage + kStagePad + 16 * c) = u32x4a{d[0], d[1], d[2], d[3]};
+        }
+    }
+}
+
+// Walks consecutive segments [s, s_end) of one wave with a one-segment
+// software pipeline: each step stages segment s into LDS and, before
+// returning, requests segment s + 1's data and segment s + 2's control bytes,
+// so that they are in flight while s is decoded and stored.
+struct Walker {
+    const uint8_t *data;    // start of the data stream
+    uint64_t data_bytes;    // bytes of the buffer from `data` on
+    uint64_t s, s_end;
+    uint64_t boff;          // byte offset of segment s in the data stream
+    SegPlan cur;            // plan of segment s
+    uint32_t sh16;          // (data + boff) mod 16
+    Span sp;                // segment s's data in flight
+    SegCtrl ahead;          // control bytes of segment s + 1
+    bool corrupt;
+};
+
+__device__ __forceinline__ void walker_begin(const DecodeArgs &p, Walker &w, uint64_t s0, uint64_t s_end,
+                                             uint64_t boff, uint32_t lane) {
+    const uint64_t nblocks = (p.n + 3) >> 2;
+    w.data = p.in + nblocks;
+    w.data_bytes = p.in_bytes - nblocks;
+    w.s = s0;
+    w.s_end = s_end;
+    w.boff = boff;
+    w.corrupt = false;
+    w.cur = plan_segment(p, s0, load_seg_ctrl(p, s0, lane), lane);
+    w.sh16 = (uint32_t)((uintptr_t)(w.data + boff) & 15u);
+    w.sp.abase = w.data + boff - w.sh16;
+    w.sp.nch = (w.sh16 + w.cur.total + 15) >> 4;
+    span_load(p, w.sp, lane);
+    w.ahead = SegCtrl{{0u, 0u, 0u, 0u}};
+    if (s0 + 1 < s_end) w.ahead = load_seg_ctrl(p, s0 + 1, lane);
+}
+
+// Stages segment w.s into `stage`, returns its plan and data alignment, and
+// advances the walker to w.s + 1 (requesting its data).
+__device__ __forceinline__ void walker_step(const DecodeArgs &p, Walker &w, uint8_t *stage, uint32_t lane,
+                                            SegPlan &seg, uint32_t &seg_sh16) {
+    if (w.boff + w.cur.total > w.data_bytes) w.corrupt = true;
+    span_to_lds(p, w.sp, stage, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    seg = w.cur;
+    seg_sh16 = w.sh16;
+    w.boff += seg.total;
+    ++w.s;
+    if (w.s < w.s_end) {
+        w.cur = plan_segment(p, w.s, w.ahead, lane);
+        const uint8_t *q = w.data + w.boff;
+        w.sh16 = (uint32_t)((uintptr_t)q & 15u);
+        w.sp.abase = q - w.sh16;
+        w.sp.nch = (w.sh16 + w.cur.total + 15) >> 4;
+        span_load(p, w.sp, lane);
+        if (w.s + 1 < w.s_end) w.ahead = load_seg_ctrl(p, w.s + 1, lane);
+    }
+}
+
+// After a staged segment has been read: the next step overwrites the staging
+// area, and LDS operations of one wave complete in order.
+__device__ __forceinline__ void walker_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The lane's 16 integers of a staged segment; integers past n read as 0.
+// Integer j of a block ends at byte o_{j+1} - 1 of the staged span.  With
+// y_j = 3 - code_j = 4 - L_j and R_j = kStagePad - 4 + o_{j+1} - 4 (j + 1),
+// which falls by y_j per integer, the 4 bytes ending at the integer's last
+// byte start at R_j + 4 (j + 1); they are cut out of the aligned 8 bytes
+// around them, and their top L_j bytes are the integer.
+__device__ __forceinline__ void extract_segment(const DecodeArgs &p, uint64_t s, const uint8_t *stage,
+                                                const SegPlan &seg, uint32_t sh16, uint32_t lane,
+                                                uint32_t (&v)[4][4]) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        uint32_t R = kStagePad - 4 + sh16 + seg.off[k];
+        const uint32_t nc = ~seg.sc.c[k];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t y = (nc >> (2 * j)) & 3u;
+            R -= y;
+            const uint32_t a = (R & ~3u) + 4 * (j + 1);
+            const uint32_t lo = *(const uint32_t *)(stage + a);
+            const uint32_t hi = *(const uint32_t *)(stage + a + 4);
+            v[k][j] = __builtin_amdgcn_alignbyte(0u, __builtin_amdgcn_alignbyte(hi, lo, R & 3u), y);
+        }
+    }
+    if (!segment_full(p, s)) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t m = block_ints(p, s, k, lane);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) v[k][j] = (j < m) ? v[k][j] : 0u;
+        }
+    }
+}
+
+// Running sum over the segment in integer order (Section 2), continuing from
+// `carry`, which it advances past the segment.
+__device__ __forceinline__ void running_sum(uint32_t (&v)[4][4], uint32_t &carry) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        v[k][1] += v[k][0];
+        v[k][2] += v[k][1];
+        v[k][3] += v[k][2];
+        const uint32_t li = wave_incl_scan(v[k][3]);
+        const uint32_t add = carry + li - v[k][3];
+        carry += wave_last(li);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) v[k][j] += add;
+    }
+}
+
+__device__ __forceinline__ void store_segment(const DecodeArgs &p, uint64_t s, uint32_t lane, const uint32_t (&v)[4][4],
+                                              uint32_t add) {
+    uint32_t *o = p.out + s * kSegInts + 4ull * lane;
+    if (segment_full(p, s)) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+            __builtin_nontemporal_store(u32x4{v[k][0] + add, v[k][1] + add, v[k][2] + add, v[k][3] + add},
+                                        (u32x4 *)(o + 4 * kWave * k));
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t m = block_ints(p, s, k, lane);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j)
+                if (j < m) o[4 * kWave * k + j] = v[k][j] + add;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// control-byte counts
+
+// Data bytes described by the P control bytes [first + P lane, first + P lane
+// + P) of stream p (Section 4: each control byte stands for 4 integers plus
+// the sum of its codes), counting only integers below n.  Reads aligned dwords
+// when the whole run of the wave lies inside the stream, else byte by byte.
+template <uint32_t P>
+__device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint64_t first,
+                                                    uint32_t lane) {
+    static_assert(P % 4 == 0, "whole dwords per lane");
+    const uint64_t nblocks = (n + 3) >> 2;
+    const uint8_t *gp = in + first;
+    const uint32_t sh = (uint32_t)((uintptr_t)gp & 3u);
+    // every block of the wave's run is full (4 integers), and the aligned
+    // dwords around it, one dword past its end included, lie in the buffer
+    if ((first + (uint64_t)P * kWave) * 4 <= n && first >= sh && first + (uint64_t)P * kWave + 4 <= in_bytes) {
+        const uint32_t *base = (const uint32_t *)(gp - sh) + (P / 4) * lane;
+        const uint32_t keep = 0xFFFFFFFFu << (8u * sh);
+        uint32_t codes = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < P / 4; ++i) {
+            const uint32_t x = (i == 0) ? (base[i] & keep) : base[i];
+            codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
+        }
+        const uint32_t e = base[P / 4] & ~keep;
+        codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
+        return 4u * P + codes;
+    }
+    const uint32_t last_r = (n & 3) ? (uint32_t)(n & 3) : 4u;
+    const uint64_t b0 = first + (uint64_t)P * lane;
+    uint32_t bytes = 0;
+    for (uint32_t i = 0; i < P; ++i) {
+        const uint64_t b = b0 + i;
+        if (b < nblocks) bytes += control_data_bytes(in[b], (b == nblocks - 1) ? last_r : 4u);
+    }
+    return bytes;
+}
+
+// --------------------------------------------------------------------------
+// encoding one segment
+
+// A stream to encode: n values at `in`; the stream (control bytes first) is
+// written at `out`.  Delta encoding starts from `start`.
+struct EncodeStream {
+    const uint32_t *in;
+    uint64_t n;
+    uint8_t *out;
+    uint32_t start;
+};
+
+constexpr uint32_t kEncStageBytes = 4160;  // 16 x 257 bytes of span + padding
+
+// The lane's four blocks of segment s: the values (or differences, Section 2)
+// to store, each block's control byte (Section 3: L = 1 + [v >= 2^8] +
+// [v >= 2^16] + [v >= 2^24], code L - 1 in bits 2j..2j+1) and data bytes.
+// Integers past n contribute nothing.
+struct SegValues {
+    uint32_t v[4][4];
+    uint32_t c[4];
+    uint32_t nb[4];
+};
+
+template <bool DELTA>
+__device__ __forceinline__ void load_segment_values(const EncodeStream &e, uint64_t s, uint32_t lane, SegValues &sv) {
+    const bool full = (s + 1) * kSegInts <= e.n;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint64_t b = s * kSegCtrl + kWave * k + lane;
+        const uint32_t *src = e.in + 4 * b;
+        uint32_t x[4] = {0u, 0u, 0u, 0u};
+        uint32_t r = 4, pv = 0;
+        if (full) {
+            const u32x4 w = *(const u32x4 *)src;
+            x[0] = w.x; x[1] = w.y; x[2] = w.z; x[3] = w.w;
+            if (DELTA) pv = b ? src[-1] : e.start;
+        } else {
+            const uint64_t i0 = 4 * b;
+            r = i0 < e.n ? (uint32_t)((e.n - i0) < 4 ? (e.n - i0) : 4) : 0u;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j)
+                if (j < r) x[j] = src[j];
+            if (DELTA && r) pv = b ? src[-1] : e.start;
+        }
+        uint32_t ctrl = 0, bytes = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t val = DELTA ? x[j] - (j ? x[j - 1] : pv) : x[j];
+            sv.v[k][j] = val;
+            const uint32_t L = byte_length(val);
+            ctrl |= (j < r) ? ((L - 1u) << (2 * j)) : 0u;
+            bytes += (j < r) ? L : 0u;
+        }
+        sv.c[k] = ctrl;
+        sv.nb[k] = bytes;
+    }
+}
+
+// Data bytes of the lane's blocks of a loaded segment, summed over the wave.
+__device__ __forceinline__ uint32_t segment_data_bytes(const SegValues &sv) {
+    return wave_last(wave_incl_scan(sv.nb[0] + sv.nb[1] + sv.nb[2] + sv.nb[3]));
+}
+
+// Writes segment s of stream e: its control bytes, and its data bytes at byte
+// `boff` of the data stream (which starts at out + ceil(n/4)).  The data are
+// packed little-endian into the wave's LDS area laid out like the 16-byte
+// aligned global span that holds them, then written with 16-byte stores
+// inside the span and byte stores at its two edges (neighbouring segments own
+// the rest of those 16-byte chunks).  Returns the segment's data bytes.
+template <bool DELTA>
+__device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64_t s, uint64_t boff, uint32_t lane,
+                                                   uint32_t *stage) {
+    SegValues sv;
+    load_segment_values<DELTA>(e, s, lane, sv);
+    uint32_t off[4], run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t incl = wave_incl_scan(sv.nb[k]);
+        off[k] = run + incl - sv.nb[k];
+        run += wave_last(incl);
+    }
+    const uint32_t total = run;
+    const uint64_t nblocks = (e.n + 3) >> 2;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint64_t b = s * kSegCtrl + kWave * k + lane;
+        if (b < nblocks) e.out[b] = (uint8_t)sv.c[k];
+    }
+    uint8_t *dst = e.out + nblocks + boff;
+    const uint32_t sh = (uint32_t)((uintptr_t)dst & 15u);
+    uint8_t *abase = dst - sh;
+    const uint32_t nch = (sh + total + 15) >> 4;
+#pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) {
+        const uint32_t c = lane + kWave * i;
+        if (c < nch) ((u32x4a *)stage)[c] = u32x4a{0u, 0u, 0u, 0u};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        uint32_t pos = sh + off[k];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t code = (sv.c[k] >> (2 * j)) & 3u;
+            const uint64_t i = (s * kSegCtrl + kWave * k + lane) * 4 + j;  // integers past n are not written
+            if (i < e.n) {
+                const uint32_t val = sv.v[k][j];
+                const uint32_t w = pos >> 2, sb = pos & 3u;
+                atomicOr(stage + w, val << (8u * sb));
+                if (sb + code + 1u > 4u) atomicOr(stage + w + 1, val >> (32u - 8u * sb));
+                pos += code + 1u;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t end = sh + total;
+#pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) {
+        const uint32_t c = lane + kWave * i;
+        if (c < nch) {
+            const uint32_t lo = 16 * c, hi = lo + 16;
+            if (lo >= sh && hi <= end) {
+                *(u32x4a *)(abase + lo) = ((const u32x4a *)stage)[c];
+            } else {
+                const uint32_t from = lo > sh ? lo : sh;
+                const uint32_t to = hi < end ? hi : end;
+                for (uint32_t q = from; q < to; ++q) abase[q] = (uint8_t)(stage[q >> 2] >> (8u * (q & 3u)));
+            }
+        }
+    }
+    // the next segment clears this area: LDS operations of a wave complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return total;
+}
+
+}  // namespace svb
