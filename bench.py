@@ -19,7 +19,10 @@ Prints one JSON line.  Besides the headline it carries:
   flushed       the whole call with a 1 GiB cache-evicting write before each;
   copy          a plain copy kernel (the practical bandwidth ceiling);
   at_2p28       delta decode of the same generator at 2^28 integers, and plain
-                decode of 2^28 integers with unpredictable lengths.
+                decode of 2^28 integers with unpredictable lengths;
+  batched       200,000 delta-coded posting lists (about 3e8 integers):
+                autotuned batched decode and encode, against the single-array
+                rate and against one svb_delta_decode call per list.
 
 `python bench.py --summarize-counters FETCH.csv WRITE.csv OUT.md` turns two
 rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) into the
@@ -276,6 +279,63 @@ def measure_copy(svb, torch, steps):
             "frac_of_peak": gbs(8 * COPY_WORDS, ms) / HBM_PEAK_GBS, "ok": ok}
 
 
+def measure_batched(svb, torch, np, inputs, steps, warmup):
+    """C4: 200,000 posting lists (rank-size Zipf lengths in [1, 2^20], about 3e8 integers, sorted sets
+    over [0, 2^31)), delta-coded from 0.  Batched encode, autotuned batched delta decode, and one
+    svb_delta_decode call per list on the same streams."""
+    import ctypes
+    vals, offs = inputs.posting_lists()
+    m = offs.size - 1
+    counts = np.diff(offs).astype(np.uint64)
+    total = int(counts.sum())
+    x_dev = torch.from_numpy(vals.view(np.int32)).cuda()
+    del vals
+    caps = (counts + 3) // 4 + 4 * counts
+    comp_off = np.zeros(m, dtype=np.uint64)
+    np.cumsum(caps[:-1], out=comp_off[1:])
+    u64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+    d_counts, d_in_off, d_comp_off = u64(counts), u64(offs[:-1]), u64(comp_off)
+    comp = torch.empty(int(caps.sum()), dtype=torch.uint8, device="cuda")
+    sizes = torch.empty(m, dtype=torch.int64, device="cuda")
+    starts = torch.zeros(m, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    enc_args = (m, d_counts, d_in_off, x_dev, d_comp_off, comp, sizes, starts, total)
+    g_enc = svb.svb_autotune_encode_batch(*enc_args)
+    ewall, ekms = timed_steps(svb, torch, lambda: svb.svb_encode_batch(*enc_args), steps, warmup)
+    nbytes = int(sizes.sum().item())
+    dec_args = (m, d_counts, d_comp_off, sizes, comp, d_in_off, out, starts, total, err)
+    g_dec = svb.svb_autotune_decode_batch(*dec_args)
+    wall, kms = timed_steps(svb, torch, lambda: svb.svb_decode_batch(*dec_args), steps, warmup)
+    ok = bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+    call_ms = 1e3 * wall / steps
+    alg = nbytes + 4 * total
+    res = {"lists": m, "integers": total, "compressed_bytes": nbytes, "chunk_decode": g_dec,
+           "chunk_encode": g_enc, "ms_per_call": call_ms, "uint32_per_s": total / (call_ms * 1e-3),
+           "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
+           "kernels_ms": kms, "round_trip_ok": ok,
+           "encode": {"ms_per_call": 1e3 * ewall / steps, "uint32_per_s": total / ewall * steps, "kernels_ms": ekms}}
+    # one svb_delta_decode call per list, same streams, same output
+    L = svb.lib()
+    h_sizes = sizes.cpu().numpy().astype(np.uint64)
+    stream = torch.cuda.current_stream().cuda_stream
+    cbase, obase = comp.data_ptr(), out.data_ptr()
+    out.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(m):
+        st = L.svb_delta_decode(int(counts[i]), cbase + int(comp_off[i]), int(h_sizes[i]),
+                                obase + 4 * int(offs[i]), 0, None, stream)
+        if st != 0:
+            raise RuntimeError("svb_delta_decode failed for list %d" % i)
+    torch.cuda.synchronize()
+    per_list_s = time.perf_counter() - t0
+    res["one_call_per_list"] = {"seconds": per_list_s, "uint32_per_s": total / per_list_s,
+                                "round_trip_ok": bool(torch.equal(out, x_dev))}
+    del x_dev, comp, out
+    return res
+
+
 def run_cpu_baseline(x, min_seconds=10.0):
     """The oracle as it stands: single-threaded scalar C delta decode of the whole array, repeated."""
     import oracle
@@ -304,9 +364,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 200,000-list batched measurement")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} -- python3 bench.py "
-                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28")
+                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28 --no-batched")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, command=args.counter_command)
@@ -387,6 +448,16 @@ def main():
         log("2^28 plain decode %.4f ms/call (%.1f%% of peak)" % (r3["ms_per_call"], 100 * r3["call_frac_of_peak"]))
         line["at_2p28"]["plain_stress"] = r3
     del flush
+    if not args.no_batched:
+        log("batched: generating 200,000 posting lists")
+        rb = measure_batched(svb, torch, np, inputs, max(5, args.steps // 2), 2)
+        assert rb["round_trip_ok"] and rb["one_call_per_list"]["round_trip_ok"], "batched decode mismatch"
+        single = line.get("at_2p28", {}).get("delta_docids", {}).get("uint32_per_s", line["value"])
+        rb["vs_single_array"] = rb["uint32_per_s"] / single
+        rb["vs_one_call_per_list"] = rb["uint32_per_s"] / rb["one_call_per_list"]["uint32_per_s"]
+        line["batched"] = rb
+        log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array, %.1fx one call per list)"
+            % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"], rb["vs_one_call_per_list"]))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         line["cpu_baseline"] = run_cpu_baseline(x)

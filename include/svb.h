@@ -126,14 +126,16 @@ int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t 
 /*
  * Batched calls (Section 5's posting lists: many lists of very uneven
  * length): m independent lists decoded or encoded by one fixed sequence of
- * launches whose work list is built on the device.  Each list is cut into
- * items of a tuned number of 1024-integer segments (one wave each); lists
- * longer than one item first get per-item byte offsets (and, for delta
- * decoding, per-item value carries) from a scan.  All array arguments are
- * DEVICE arrays of m entries; the host never reads them.
+ * launches whose work list is built on the device.  A task is one
+ * 1024-integer segment of one list; each wave of the main pass takes a tuned
+ * number of consecutive tasks.  Lists longer than one segment first get
+ * per-segment byte offsets (and, for delta decoding, per-segment value
+ * carries) from a scan.  All array arguments are DEVICE arrays of m entries;
+ * the host never reads them.
  *
  * total_ints (host value) is an upper bound on sum(counts[i]); it sizes the
- * library's scratch (about 24 bytes per item).  If the counts add up to more,
+ * library's scratch (about 96 bytes per segment, m + total_ints/1024
+ * segments at most).  If the counts add up to more,
  * nothing is done: decode sets err to SVB_BATCH_OVERFLOW and encode writes
  * UINT64_MAX to every out_bytes[i].
  *
@@ -173,24 +175,70 @@ int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                      void *stream);
 
 /*
- * Autotuning of the batched calls: the item size (1, 2, 4 or 8 segments of
- * 1024 integers per wave) is chosen per device and per kind of call (decode
- * or encode, plain or delta).  svb_autotune_decode_batch times each candidate
- * on the given batch (the arguments of svb_decode_batch; it decodes the batch
- * several times and synchronises the stream), keeps the fastest for later
- * calls of that kind on the current device, and writes it to *item_segs.
- * svb_autotune_encode_batch does the same for encoding.
- * svb_set_batch_item_segments(kind, segs) sets the choice directly;
- * kind = 2 * (encode ? 1 : 0) + (delta ? 1 : 0).  The default is 2.
+ * Autotuning of the batched calls: the number of consecutive tasks a wave
+ * takes (1, 2, 4, 8 or 16 segments of 1024 integers) is chosen per device and
+ * per kind of call (decode or encode, plain or delta).
+ * svb_autotune_decode_batch times each candidate on the given batch (the
+ * arguments of svb_decode_batch; it decodes the batch several times and
+ * synchronises the stream), keeps the fastest for later calls of that kind on
+ * the current device, and writes it to *chunk.  svb_autotune_encode_batch
+ * does the same for encoding.  svb_set_batch_chunk(kind, chunk) sets the
+ * choice directly; kind = 2 * (encode ? 1 : 0) + (delta ? 1 : 0).  The
+ * default is 4.
  */
 int svb_autotune_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                               const uint64_t *in_bytes, const uint8_t *in, const uint64_t *out_off,
                               uint32_t *out, const uint32_t *starts, uint64_t total_ints, uint32_t *err,
-                              uint32_t *item_segs, void *stream);
+                              uint32_t *chunk, void *stream);
 int svb_autotune_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
                               const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes,
-                              const uint32_t *starts, uint64_t total_ints, uint32_t *item_segs, void *stream);
-int svb_set_batch_item_segments(int kind, uint32_t item_segs);
+                              const uint32_t *starts, uint64_t total_ints, uint32_t *chunk, void *stream);
+int svb_set_batch_chunk(int kind, uint32_t chunk);
+
+/*
+ * Serving runtime: a pool of lists resident in device memory and queries of
+ * a few lists each, decoded with admission by output memory and continuous
+ * batching over the batched decoder (the paper's setting of Section 5: a
+ * search engine decoding the posting lists a query asks for).
+ *
+ * svb_server_create copies the pool table to the host once: m lists whose
+ * streams lie in `in` at in_off[i] (in_bytes[i] bytes, counts[i] integers),
+ * delta-coded from starts[i] if `starts` is not NULL (all device arrays; they
+ * and `in` must stay valid while the server lives).  The server owns an output
+ * arena of arena_bytes, `streams` stream slots (1..16; a slot runs one batch
+ * at a time) and launches at most max_batch_lists lists per batch.
+ *
+ * svb_server_submit queues query `query_id` (unique among live queries) for
+ * the k lists list_ids[] (host array).  Its result is the k lists decoded back
+ * to back into one arena range.  A query whose output exceeds the arena, or
+ * with k > max_batch_lists, is refused with SVB_ERR_INVALID.
+ *
+ * svb_server_step runs one scheduling step: retire finished batches, admit
+ * waiting queries in arrival order while the arena has room for their output,
+ * and launch one batch of all admitted queries on a free slot.  With block != 0
+ * and nothing complete yet, it waits for the oldest batch on the device.  It
+ * returns the number of complete queries not yet polled (or a negative status).
+ *
+ * svb_server_poll hands out up to `cap` complete queries: id, arena offset and
+ * length (in uint32 units); their arena ranges stay reserved until
+ * svb_server_release(query_id).  svb_server_arena returns the arena's device
+ * address.  svb_server_stats writes up to `cap` counters: batches, lists,
+ * integers, queries admitted, queries completed, most slots busy at once, the
+ * decoders' err flags (OR), arena peak (integers), queries waiting, admitted
+ * but not launched, arena integers in use.  svb_server_destroy waits for the
+ * device and frees everything.  One server may be driven from one thread at a
+ * time (calls are serialised by a lock).
+ */
+int svb_server_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                      const uint8_t *in, const uint32_t *starts, uint64_t arena_bytes, uint32_t streams,
+                      uint32_t max_batch_lists, void **server);
+int svb_server_submit(void *server, uint64_t query_id, uint32_t k, const uint32_t *list_ids);
+int svb_server_step(void *server, int block);
+int svb_server_poll(void *server, uint64_t *ids, uint64_t *arena_off, uint64_t *ints, uint32_t cap);
+int svb_server_release(void *server, uint64_t query_id);
+uint32_t *svb_server_arena(void *server);
+int svb_server_stats(void *server, uint64_t *out, uint32_t cap);
+int svb_server_destroy(void *server);
 
 /* Message for a status code (static string). */
 const char *svb_strerror(int status);
@@ -209,8 +257,9 @@ void svb_release_workspace(void);
  * there were (or a negative svb_status).  Kernel names: "group_bytes",
  * "scan_offsets", "group_sums", "scan_sums", "decode", "decode_delta",
  * "encode", "encode_delta", and for the batched calls "batch_count",
- * "batch_scan_lists", "batch_map", "batch_item_bytes", "batch_scan_offsets",
- * "batch_item_sums", "batch_scan_sums", "batch_decode", "batch_encode" (a
+ * "batch_scan_lists", "batch_map", "batch_task_bytes", "batch_scan_offsets",
+ * "batch_desc", "batch_task_sums", "batch_scan_sums", "batch_carries",
+ * "batch_decode", "batch_encode" (a
  * scan of more than 65536 values is three kernels under one name).
  */
 int svb_set_kernel_timing(int enable);

@@ -16,7 +16,9 @@ __all__ = [
     "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_encode_batch", "svb_decode_batch",
     "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
-    "svb_set_batch_item_segments", "encode", "decode", "LIB_PATH",
+    "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
+    "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "encode", "decode",
+    "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
@@ -53,7 +55,15 @@ def lib():
             "svb_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp]),
             "svb_autotune_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp, vp]),
             "svb_autotune_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp]),
-            "svb_set_batch_item_segments": (i32, [i32, u32]),
+            "svb_set_batch_chunk": (i32, [i32, u32]),
+            "svb_server_create": (i32, [u32, vp, vp, vp, vp, vp, u64, u32, u32, vp]),
+            "svb_server_submit": (i32, [vp, u64, u32, vp]),
+            "svb_server_step": (i32, [vp, i32]),
+            "svb_server_poll": (i32, [vp, vp, vp, vp, u32]),
+            "svb_server_release": (i32, [vp, u64]),
+            "svb_server_arena": (vp, [vp]),
+            "svb_server_stats": (i32, [vp, vp, u32]),
+            "svb_server_destroy": (i32, [vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -97,6 +107,13 @@ def _stream(stream):
 
 def _check(status, what):
     if status != 0:
+        raise SvbError(status, what)
+    return status
+
+
+def _check_count(status, what):
+    """For calls that return a count (>= 0) or a negative svb_status."""
+    if status < 0:
         raise SvbError(status, what)
     return status
 
@@ -148,7 +165,8 @@ def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None
 
 def svb_autotune_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=0,
                               err=None, stream=None):
-    """Times each item size on this batch, keeps the fastest for later calls; returns it."""
+    """Times each chunk choice (consecutive tasks per wave) on this batch, keeps the fastest for
+    later calls of this kind; returns it."""
     chosen = ctypes.c_uint32(0)
     _check(lib().svb_autotune_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
                                            _ptr(out_off), _ptr(out), _ptr(starts), int(total_ints), _ptr(err),
@@ -165,9 +183,9 @@ def svb_autotune_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=No
     return int(chosen.value)
 
 
-def svb_set_batch_item_segments(kind, item_segs):
-    """kind = 2 * encode + delta; item_segs in {1, 2, 4, 8}."""
-    return _check(lib().svb_set_batch_item_segments(int(kind), int(item_segs)), "svb_set_batch_item_segments")
+def svb_set_batch_chunk(kind, chunk):
+    """kind = 2 * encode + delta; chunk (consecutive tasks per wave) in {1, 2, 4, 8, 16}."""
+    return _check(lib().svb_set_batch_chunk(int(kind), int(chunk)), "svb_set_batch_chunk")
 
 
 def svb_strerror(status):
@@ -204,6 +222,61 @@ def svb_kernel_times(cap=4096):
     if n < 0:
         raise SvbError(n, "svb_kernel_times")
     return [(names[i].decode(), float(ms[i])) for i in range(min(n, cap))]
+
+
+def svb_server_create(m, counts, in_off, in_bytes, inp, starts, arena_bytes, streams=4, max_batch_lists=8192):
+    """Returns the server handle (an int)."""
+    h = ctypes.c_void_p()
+    _check(lib().svb_server_create(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp), _ptr(starts),
+                                   int(arena_bytes), int(streams), int(max_batch_lists), ctypes.addressof(h)),
+           "svb_server_create")
+    return h.value
+
+
+def svb_server_submit(server, query_id, list_ids):
+    """list_ids: host sequence of list indices."""
+    import numpy as np
+    ids = np.ascontiguousarray(list_ids, dtype=np.uint32)
+    return _check(lib().svb_server_submit(server, int(query_id), int(ids.size), ids.ctypes.data), "svb_server_submit")
+
+
+def svb_server_step(server, block=False):
+    """Returns the number of completed queries not yet polled."""
+    return _check_count(lib().svb_server_step(server, 1 if block else 0), "svb_server_step")
+
+
+def svb_server_poll(server, cap=4096):
+    """[(query id, arena offset, integers)] of queries completed since the last poll."""
+    import numpy as np
+    ids = np.zeros(cap, dtype=np.uint64)
+    off = np.zeros(cap, dtype=np.uint64)
+    n = np.zeros(cap, dtype=np.uint64)
+    k = _check_count(lib().svb_server_poll(server, ids.ctypes.data, off.ctypes.data, n.ctypes.data, int(cap)),
+               "svb_server_poll")
+    return [(int(ids[i]), int(off[i]), int(n[i])) for i in range(k)]
+
+
+def svb_server_release(server, query_id):
+    return _check(lib().svb_server_release(server, int(query_id)), "svb_server_release")
+
+
+def svb_server_arena(server):
+    return lib().svb_server_arena(server)
+
+
+SERVER_STATS = ("batches", "lists", "integers", "admitted", "completed", "peak_busy_slots", "err",
+                "arena_peak_ints", "waiting", "admitted_not_launched", "arena_in_use_ints")
+
+
+def svb_server_stats(server):
+    import numpy as np
+    out = np.zeros(len(SERVER_STATS), dtype=np.uint64)
+    _check(lib().svb_server_stats(server, out.ctypes.data, len(SERVER_STATS)), "svb_server_stats")
+    return {k: int(v) for k, v in zip(SERVER_STATS, out)}
+
+
+def svb_server_destroy(server):
+    return _check(lib().svb_server_destroy(server), "svb_server_destroy")
 
 
 # ------------------------------------------------------------------ conveniences

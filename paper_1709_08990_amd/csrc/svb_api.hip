@@ -275,17 +275,18 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
 
 // ---------------------------------------------------------------- batched calls
 
-// Item size (segments per wave) per (device, kind); kind = 2 encode + delta.
-std::map<std::pair<int, int>, uint32_t> g_item_segs;
-constexpr uint32_t kDefaultItemSegs = 2;
+// Tasks (segments) per wave of the main pass, per (device, kind); kind = 2 encode + delta.
+std::map<std::pair<int, int>, uint32_t> g_chunk;
+constexpr uint32_t kDefaultChunk = 4;
+constexpr uint32_t kChunkChoices[] = {1, 2, 4, 8, 16};
 
-bool valid_item_segs(uint32_t g) { return g == 1 || g == 2 || g == 4 || g == 8; }
+bool valid_chunk(uint32_t c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
 
-uint32_t tuned_item_segs(int kind) {
+uint32_t tuned_chunk(int kind) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    auto it = g_item_segs.find(std::make_pair(dev, kind));
-    return it == g_item_segs.end() ? kDefaultItemSegs : it->second;
+    auto it = g_chunk.find(std::make_pair(dev, kind));
+    return it == g_chunk.end() ? kDefaultChunk : it->second;
 }
 
 struct BatchCall {
@@ -301,10 +302,11 @@ struct BatchCall {
     uint32_t *err;
 };
 
-// item_segs = 0: the tuned choice for this kind of call.
-int do_batch(const BatchCall &c, uint32_t item_segs, void *stream) {
+// chunk = 0: the tuned choice for this kind of call.
+int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (c.m == 0) return SVB_OK;
+    if (c.m >= (1u << 31)) return SVB_ERR_INVALID;
     if (!c.counts || !c.in_off || !c.in || !c.out_off || !c.out) return SVB_ERR_INVALID;
     if (!c.encode && !c.in_bytes) return SVB_ERR_INVALID;
     if (!aligned8(c.counts) || !aligned8(c.in_off) || !aligned8(c.out_off)) return SVB_ERR_INVALID;
@@ -314,21 +316,22 @@ int do_batch(const BatchCall &c, uint32_t item_segs, void *stream) {
     const bool delta = c.starts != nullptr;
     const int kind = 2 * (c.encode ? 1 : 0) + (delta ? 1 : 0);
     std::lock_guard<std::mutex> lock(g_mu);
-    const uint32_t G = item_segs ? item_segs : tuned_item_segs(kind);
-    if (!valid_item_segs(G)) return SVB_ERR_INVALID;
-    const uint64_t per_item = (uint64_t)G * kSegInts;
-    const uint64_t t_cap64 = (uint64_t)c.m + (c.total_ints + per_item - 1) / per_item;
+    const uint32_t C = chunk ? chunk : tuned_chunk(kind);
+    if (!valid_chunk(C)) return SVB_ERR_INVALID;
+    const uint64_t t_cap64 = (uint64_t)c.m + (c.total_ints + kSegInts - 1) / kSegInts;
     if (c.total_ints > (1ull << 50) || t_cap64 >= (1ull << 31)) return SVB_ERR_INVALID;
     const uint64_t T = t_cap64, M = c.m;
     auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
     const uint64_t o_litems = 0;
     const uint64_t o_lbase = o_litems + up16(4 * M);
     const uint64_t o_ilist = o_lbase + up16(4 * (M + 1));
-    const uint64_t o_ibytes = o_ilist + up16(4 * T);
+    const uint64_t o_ifirst = o_ilist + up16(4 * T);
+    const uint64_t o_ibytes = o_ifirst + up16(4 * T);
     const uint64_t o_ioff = o_ibytes + up16(4 * T);
     const uint64_t o_ivsum = o_ioff + up16(8 * T);
     const uint64_t o_ivpre = o_ivsum + up16(4 * T);
-    const uint64_t o_scan = o_ivpre + up16(4 * T);
+    const uint64_t o_desc = (o_ivpre + up16(4 * T) + 63) & ~63ull;
+    const uint64_t o_scan = o_desc + 64 * T;
     const uint64_t scan_bytes = std::max(scan_scratch_bytes(M), scan_scratch_bytes(T));
     const uint64_t need = o_scan + up16(scan_bytes);
     Workspace *w;
@@ -352,14 +355,17 @@ int do_batch(const BatchCall &c, uint32_t item_segs, void *stream) {
     a.litems = (uint32_t *)(sc + o_litems);
     a.lbase = (uint32_t *)(sc + o_lbase);
     a.item_list = (uint32_t *)(sc + o_ilist);
+    a.item_first = (uint32_t *)(sc + o_ifirst);
     a.t_cap = (uint32_t)T;
+    a.chunk = C;
     a.ibytes = (uint32_t *)(sc + o_ibytes);
     a.ioff = (uint64_t *)(sc + o_ioff);
     a.ivsum = (uint32_t *)(sc + o_ivsum);
     a.ivpre = (uint32_t *)(sc + o_ivpre);
+    a.desc = (TaskDesc *)(sc + o_desc);
     void *scan_scr = sc + o_scan;
     auto run = [&](const char *name, int phase) {
-        return hip_status(timed(name, s, [&] { return launch_batch(a, G, phase, c.encode, delta, s); }));
+        return hip_status(timed(name, s, [&] { return launch_batch(a, phase, c.encode, delta, s); }));
     };
     if ((st = run("batch_count", kBatchCount)) != SVB_OK) return st;
     if ((st = hip_status(timed("batch_scan_lists", s, [&] {
@@ -367,22 +373,24 @@ int do_batch(const BatchCall &c, uint32_t item_segs, void *stream) {
          }))) != SVB_OK)
         return st;
     if ((st = run("batch_map", kBatchMap)) != SVB_OK) return st;
-    if ((st = run("batch_item_bytes", kBatchItemBytes)) != SVB_OK) return st;
+    if ((st = run("batch_task_bytes", kBatchItemBytes)) != SVB_OK) return st;
     if ((st = hip_status(timed("batch_scan_offsets", s, [&] {
              return launch_scan(a.ibytes, a.ioff, T, true, 0u, s, nullptr, scan_scr);
          }))) != SVB_OK)
         return st;
+    if ((st = run("batch_desc", kBatchDesc)) != SVB_OK) return st;
     if (!c.encode && delta) {
-        if ((st = run("batch_item_sums", kBatchItemSums)) != SVB_OK) return st;
+        if ((st = run("batch_task_sums", kBatchItemSums)) != SVB_OK) return st;
         if ((st = hip_status(timed("batch_scan_sums", s, [&] {
                  return launch_scan(a.ivsum, a.ivpre, T, false, 0u, s, nullptr, scan_scr);
              }))) != SVB_OK)
             return st;
+        if ((st = run("batch_carries", kBatchCarries)) != SVB_OK) return st;
     }
     return run(c.encode ? "batch_encode" : "batch_decode", kBatchWork);
 }
 
-// Times each item size on the caller's batch and keeps the fastest.
+// Times each chunk choice on the caller's batch and keeps the fastest.
 int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -391,11 +399,10 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
         (void)hipEventDestroy(e0);
         return SVB_ERR_HIP;
     }
-    const uint32_t candidates[] = {1, 2, 4, 8};
-    uint32_t best = kDefaultItemSegs;
+    uint32_t best = kDefaultChunk;
     float best_ms = 1e30f;
     int st = SVB_OK;
-    for (uint32_t g : candidates) {
+    for (uint32_t g : kChunkChoices) {
         for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_batch(c, g, stream);
         if (st != SVB_OK) break;
         float times[3];
@@ -420,7 +427,7 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
     (void)hipGetDevice(&dev);
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        g_item_segs[std::make_pair(dev, 2 * (c.encode ? 1 : 0) + (c.starts ? 1 : 0))] = best;
+        g_chunk[std::make_pair(dev, 2 * (c.encode ? 1 : 0) + (c.starts ? 1 : 0))] = best;
     }
     if (chosen) *chosen = best;
     return SVB_OK;
@@ -452,6 +459,14 @@ uint32_t persistent_grid(const void *kernel, uint32_t num_tiles, uint32_t block_
     }
     if (grid > num_tiles) grid = num_tiles;
     return grid ? grid : 1u;
+}
+
+// Batched decode for the serving runtime (same path as svb_decode_batch).
+int serve_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                       const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
+                       uint64_t total_ints, uint32_t *err, void *stream) {
+    BatchCall c = {false, m, counts, in_off, in_bytes, in, out_off, out, nullptr, starts, total_ints, err};
+    return do_batch(c, 0, stream);
 }
 
 }  // namespace svb
@@ -498,24 +513,24 @@ int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
 
 int svb_autotune_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
                               const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
-                              uint64_t total_ints, uint32_t *err, uint32_t *item_segs, void *stream) {
+                              uint64_t total_ints, uint32_t *err, uint32_t *chunk, void *stream) {
     BatchCall c = {false, m, counts, in_off, in_bytes, in, out_off, out, nullptr, starts, total_ints, err};
-    return autotune_batch(c, item_segs, stream);
+    return autotune_batch(c, chunk, stream);
 }
 
 int svb_autotune_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
                               const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes, const uint32_t *starts,
-                              uint64_t total_ints, uint32_t *item_segs, void *stream) {
+                              uint64_t total_ints, uint32_t *chunk, void *stream) {
     BatchCall c = {true, m, counts, in_off, nullptr, in, out_off, out, out_bytes, starts, total_ints, nullptr};
-    return autotune_batch(c, item_segs, stream);
+    return autotune_batch(c, chunk, stream);
 }
 
-int svb_set_batch_item_segments(int kind, uint32_t item_segs) {
-    if (kind < 0 || kind > 3 || !valid_item_segs(item_segs)) return SVB_ERR_INVALID;
+int svb_set_batch_chunk(int kind, uint32_t chunk) {
+    if (kind < 0 || kind > 3 || !valid_chunk(chunk)) return SVB_ERR_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
     std::lock_guard<std::mutex> lock(g_mu);
-    g_item_segs[std::make_pair(dev, kind)] = item_segs;
+    g_chunk[std::make_pair(dev, kind)] = chunk;
     return SVB_OK;
 }
 

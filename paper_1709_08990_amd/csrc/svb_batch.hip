@@ -1,23 +1,33 @@
 // Batched Stream VByte: m independent lists (the paper's posting lists,
-// Section 5: many lists of very uneven length) decoded or encoded by one
+// Section 5: many lists of very uneven length) decoded or encoded by one fixed
 // sequence of launches whose work list is built on the device.
 //
-// Every list is cut into items of G segments (G * 1024 integers); an item is
-// one wave's work.  The host never reads the list arrays, so the item list is
-// built on the device:
-//   1. batch_count_kernel:  items per list (0 for an empty or invalid list);
-//   2. scan -> each list's first item, and the item total;
-//   3. batch_map_kernel:    item -> list;
-//   4. batch_item_bytes_kernel: data bytes of every item that is not the last
-//      of its list (control bytes only when decoding; the values' byte lengths
-//      when encoding), then a scan -> each item's byte offset in its list's
-//      data stream (global scan minus the value at the list's first item);
-//   5. delta decoding only: batch_item_sums_kernel sums the stored differences
-//      of every item that is not the last of its list, then a scan -> each
-//      item's carry;
-//   6. batch_decode_kernel / batch_encode_kernel: one wave per item.
-// A list that fits in one item skips steps 4-5 entirely (offset 0, carry =
-// start), so short lists cost one pass over their bytes.
+// A task is one 1024-integer segment of one list.  Tasks are numbered list by
+// list; the host never reads the list arrays, so the task list is built on
+// the device:
+//   1. batch_count_kernel:  segments per list (0 for an empty or invalid list);
+//   2. scan -> each list's first task, and the task total;
+//   3. batch_map_kernel:    task -> (list, last segment of its list?), first
+//      task of its list;
+//   4. batch_task_bytes_kernel: data bytes of every task that is not the last
+//      segment of its list (8 tasks per wave when decoding: 8 lanes read a
+//      segment's 256 control bytes; one task per wave when encoding: the byte
+//      lengths of its 1024 values), then a scan -> each task's byte offset in
+//      its list's data stream (global scan minus the value at the list's
+//      first task);
+//   5. delta decoding only: batch_walk_kernel in value-sum mode sums the
+//      stored differences of every task that is not the last of its list,
+//      then a scan -> each task's carry (global scan minus the value at the
+//      list's first task, plus the list's start);
+//   5b. batch_desc_kernel / batch_carry_kernel: one 64-byte descriptor per task
+//      (stream, output, segment, byte offset, carry), so a wave needs a single
+//      load to start a task;
+//   6. batch_walk_kernel / batch_encode_kernel: each wave takes a run of
+//      `chunk` consecutive tasks (the tuned parameter).  The decoder keeps a
+//      pipeline three tasks deep: while one segment is decoded from LDS, the
+//      next task's data, the control bytes of the one after and the
+//      descriptor of the third are in flight.
+// A list of one segment needs none of steps 4-5: offset 0, carry = start.
 #include "svb_device.hpp"
 #include "svb_internal.hpp"
 #include "svb_segment.hpp"
@@ -27,253 +37,413 @@ namespace svb {
 namespace {
 
 constexpr uint32_t kEncStageWords = kEncStageBytes / 4;
+constexpr uint32_t kLastBit = 1u << 31;
 
-__device__ __forceinline__ uint32_t items_of(uint64_t count, uint32_t G) {
-    const uint64_t per = (uint64_t)G * kSegInts;
-    return (uint32_t)((count + per - 1) / per);
-}
-
-template <uint32_t G>
+template <bool ENCODE>
 __global__ __launch_bounds__(kThreads) void batch_count_kernel(BatchArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= a.m) return;
     const uint64_t c = a.counts[i];
-    uint32_t items = 0;
+    uint32_t segs = 0;
     if (c > SVB_MAX_N) {
-        if (a.err) *a.err = SVB_DECODE_CORRUPT;
-        if (a.out_bytes) a.out_bytes[i] = ~0ull;
-    } else if (a.in_bytes && a.in_bytes[i] < (c + 3) / 4) {
+        if (!ENCODE && a.err) *a.err = SVB_DECODE_CORRUPT;
+        if (ENCODE && a.out_bytes) a.out_bytes[i] = ~0ull;
+    } else if (!ENCODE && a.in_bytes[i] < (c + 3) / 4) {
         if (a.err) *a.err = SVB_DECODE_CORRUPT;  // control stream longer than the list's bytes
     } else {
-        items = items_of(c, G);
-        if (c == 0 && a.out_bytes) a.out_bytes[i] = 0;
+        segs = (uint32_t)((c + kSegInts - 1) / kSegInts);
+        if (ENCODE && c == 0 && a.out_bytes) a.out_bytes[i] = 0;
     }
-    a.litems[i] = items;
+    a.litems[i] = segs;
 }
 
+__device__ __forceinline__ void map_task(const BatchArgs &a, uint32_t t, uint32_t i, uint32_t b, uint32_t e) {
+    a.item_list[t] = i | (t + 1 == e ? kLastBit : 0u);
+    a.item_first[t] = b;
+}
+
+// Task -> list.  A thread maps the tasks of its own list when there are at
+// most 64 of them; the lanes of the wave share the longer lists.
 __global__ __launch_bounds__(kThreads) void batch_map_kernel(BatchArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.m) return;
-    if (a.lbase[a.m] > a.t_cap) {
+    const bool overflow = a.lbase[a.m] > a.t_cap;
+    const bool mine = i < a.m;
+    if (overflow) {
         // the caller's integer bound was too small: nothing is done
         if (i == 0 && a.err) *a.err = SVB_BATCH_OVERFLOW;
-        if (a.out_bytes) a.out_bytes[i] = ~0ull;
+        if (mine && a.out_bytes) a.out_bytes[i] = ~0ull;
         return;
     }
-    const uint32_t b = a.lbase[i], e = b + a.litems[i];
-    for (uint32_t t = b; t < e; ++t) a.item_list[t] = (uint32_t)i;
+    uint32_t b = 0, e = 0;
+    if (mine) {
+        b = a.lbase[i];
+        e = b + a.litems[i];
+    }
+    const bool longer = e - b > (uint32_t)kWave;
+    if (mine && !longer)
+        for (uint32_t t = b; t < e; ++t) map_task(a, t, (uint32_t)i, b, e);
+    uint64_t todo = __ballot(mine && longer);
+    while (todo) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, l);
+        const uint32_t el = (uint32_t)__builtin_amdgcn_readlane((int)e, l);
+        const uint32_t il = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, l);
+        for (uint32_t t = bl + lane; t < el; t += kWave) map_task(a, t, il, bl, el);
+    }
 }
 
-// The item a wave works on, and its place in its list.
-struct ItemRef {
+// Total tasks, or 0 if they overflow the scratch.
+__device__ __forceinline__ uint32_t task_total(const BatchArgs &a) {
+    const uint32_t total = a.lbase[a.m];
+    return total > a.t_cap ? 0u : total;
+}
+
+// ---------------------------------------------------------------- decoding
+
+// Wave-uniform copies of descriptor fields (in scalar registers).  The
+// builtin works on int: each half goes back to uint32_t before widening, so
+// no half is sign-extended.
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32) | (uint64_t)uniform32((uint32_t)x);
+}
+
+// Descriptors, written once every task's byte offset (and carry) is known.
+template <bool ENCODE>
+__global__ __launch_bounds__(kThreads) void batch_desc_kernel(BatchArgs a) {
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= task_total(a)) return;
+    const uint32_t word = a.item_list[t];
+    const uint32_t first = a.item_first[t];
+    const uint32_t i = word & ~kLastBit;
+    TaskDesc d = {};
+    if (ENCODE) {
+        d.in = (uint64_t)(a.in32 + a.in_off[i]);
+        d.out = (uint64_t)(a.out8 + a.out_off[i]);
+        d.carry = a.starts ? a.starts[i] : 0u;
+    } else {
+        d.in = (uint64_t)(a.in8 + a.in_off[i]);
+        d.in_bytes = a.in_bytes[i];
+        d.out = (uint64_t)(a.out32 + a.out_off[i]);
+    }
+    d.n = a.counts[i];
+    d.boff = a.ioff[t] - a.ioff[first];
+    d.s = (uint32_t)t - first;
+    d.word = word;
+    a.desc[t] = d;
+}
+
+// Delta decoding: the running sum before each task.
+__global__ __launch_bounds__(kThreads) void batch_carry_kernel(BatchArgs a) {
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= task_total(a)) return;
+    const uint32_t first = a.item_first[t];
+    const uint32_t i = a.item_list[t] & ~kLastBit;
+    a.desc[t].carry = a.starts[i] + (a.ivpre[t] - a.ivpre[first]);
+}
+
+// A decode task as a wave sees it (wave-uniform).
+struct TaskHdr {
     bool valid;
-    uint32_t list;
-    uint32_t first_item;  // the list's first item
-    uint32_t piece;       // item index inside the list
     bool last;
+    DecodeArgs p;
+    uint64_t s;
+    uint64_t boff;
+    uint32_t carry;
 };
 
-__device__ __forceinline__ ItemRef item_ref(const BatchArgs &a, uint64_t t) {
-    ItemRef r = {false, 0u, 0u, 0u, false};
-    const uint32_t total = a.lbase[a.m];
-    if (total > a.t_cap || t >= total) return r;
-    r.valid = true;
-    r.list = a.item_list[t];
-    r.first_item = a.lbase[r.list];
-    r.piece = (uint32_t)t - r.first_item;
-    r.last = r.piece + 1 == a.litems[r.list];
-    return r;
+__device__ __forceinline__ TaskHdr load_hdr(const BatchArgs &a, uint64_t t, uint64_t t_end) {
+    TaskHdr h = {};
+    h.valid = t < t_end;
+    if (!h.valid) return h;
+    const TaskDesc d = a.desc[t];
+    h.p.in = (const uint8_t *)uniform64(d.in);
+    h.p.in_bytes = uniform64(d.in_bytes);
+    h.p.n = uniform64(d.n);
+    h.p.out = (uint32_t *)uniform64(d.out);
+    h.p.err = a.err;
+    h.boff = uniform64(d.boff);
+    h.s = uniform32(d.s);
+    h.carry = uniform32(d.carry);
+    h.last = (uniform32(d.word) & kLastBit) != 0;
+    return h;
 }
 
-__device__ __forceinline__ DecodeArgs list_stream(const BatchArgs &a, uint32_t i) {
-    DecodeArgs p = {};
-    p.in = a.in8 + a.in_off[i];
-    p.in_bytes = a.in_bytes[i];
-    p.n = a.counts[i];
-    p.out = a.out32 + a.out_off[i];
-    p.err = a.err;
-    return p;
+// A task's segment in flight: its plan and its data loads.
+struct Pending {
+    SegPlan plan;
+    uint32_t sh16;
+    Span sp;
+};
+
+__device__ __forceinline__ void issue_task(const TaskHdr &k, const SegCtrl &sc, uint32_t lane, Pending &pd) {
+    pd.plan = plan_segment(k.p, k.s, sc, lane);
+    const uint8_t *q = k.p.in + (k.p.n + 3) / 4 + k.boff;
+    pd.sh16 = (uint32_t)((uintptr_t)q & 15u);
+    pd.sp.abase = q - pd.sh16;
+    pd.sp.nch = (pd.sh16 + pd.plan.total + 15) >> 4;
+    span_load(k.p, pd.sp, lane);
 }
 
-__device__ __forceinline__ EncodeStream list_values(const BatchArgs &a, uint32_t i) {
-    EncodeStream e;
-    e.in = a.in32 + a.in_off[i];
-    e.n = a.counts[i];
-    e.out = a.out8 + a.out_off[i];
-    e.start = a.starts ? a.starts[i] : 0u;
-    return e;
-}
-
-__device__ __forceinline__ uint64_t wave_item(uint32_t wave) { return (uint64_t)blockIdx.x * kWaves + wave; }
-
-// Data bytes of every item that is not the last of its list.
-template <uint32_t G, bool ENCODE, bool DELTA>
-__global__ __launch_bounds__(kThreads) void batch_item_bytes_kernel(BatchArgs a) {
+// Walks tasks [t0, t0 + chunk) of the task list with a pipeline three tasks
+// deep: in the iteration that decodes task t, the data of t + 1, the control
+// bytes of t + 2 and the descriptor of t + 3 are requested, each from what the
+// previous iteration loaded.
+//   kPlain / kDelta: decode and store (delta: running sum from the task's carry);
+//   kSums: for tasks that are not the last segment of their list, write the
+//          sum of the stored differences to ivsum (other tasks are skipped).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void batch_walk_kernel(BatchArgs a) {
+    constexpr bool DELTA = MODE == kDelta;
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t t = wave_item(wave);
-    const ItemRef r = item_ref(a, t);
-    if (!r.valid) return;
-    uint32_t bytes = 0;
-    if (!r.last) {
-        if (ENCODE) {
-            const EncodeStream e = list_values(a, r.list);
+    const uint32_t total = task_total(a);
+    const uint64_t t0 = ((uint64_t)blockIdx.x * kWaves + wave) * a.chunk;
+    if (t0 >= total) return;
+    const uint64_t t_end = t0 + a.chunk < total ? t0 + a.chunk : total;
+    uint8_t *stage = s_stage + wave * kStageBytes;
+    bool corrupt = false;
+
+    // in the value-sum pass only tasks that are not the last of their list work
+    auto active = [&](const TaskHdr &k) { return k.valid && (MODE != kSums || !k.last); };
+    TaskHdr h0 = load_hdr(a, t0, t_end);
+    Pending pend;
+    if (active(h0)) issue_task(h0, load_seg_ctrl(h0.p, h0.s, lane), lane, pend);
+    TaskHdr h1 = load_hdr(a, t0 + 1, t_end);
+    TaskHdr h2 = load_hdr(a, t0 + 2, t_end);
+    SegCtrl c1 = {{0u, 0u, 0u, 0u}};
+    if (active(h1)) c1 = load_seg_ctrl(h1.p, h1.s, lane);
+
 #pragma unroll 1
-            for (uint32_t g = 0; g < G; ++g) {
-                SegValues sv;
-                load_segment_values<DELTA>(e, (uint64_t)r.piece * G + g, lane, sv);
-                bytes += segment_data_bytes(sv);
-            }
-        } else {
-            const DecodeArgs p = list_stream(a, r.list);
-            const uint32_t lb = lane_ctrl_bytes<4 * G>(p.in, p.in_bytes, p.n, (uint64_t)r.piece * G * kSegCtrl, lane);
-            bytes = wave_last(wave_incl_scan(lb));
+    for (uint64_t t = t0; t < t_end; ++t) {
+        const TaskHdr k = h0;
+        const bool work = active(k);
+        SegPlan seg;
+        uint32_t sh16 = 0;
+        if (work) {
+            if (k.boff + pend.plan.total > k.p.in_bytes - (k.p.n + 3) / 4) corrupt = true;
+            span_to_lds(k.p, pend.sp, stage, lane);
+            seg = pend.plan;
+            sh16 = pend.sh16;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (active(h1)) issue_task(h1, c1, lane, pend);
+        SegCtrl c2 = {{0u, 0u, 0u, 0u}};
+        if (active(h2)) c2 = load_seg_ctrl(h2.p, h2.s, lane);
+        const TaskHdr h3 = load_hdr(a, t + 3, t_end);
+
+        if (work) {
+            uint32_t v[4][4];
+            extract_segment(k.p, k.s, stage, seg, sh16, lane, v);
+            if (MODE == kSums) {
+                uint32_t x = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) x += v[q][0] + v[q][1] + v[q][2] + v[q][3];
+                x = wave_last(wave_incl_scan(x));
+                if (lane == 0) a.ivsum[t] = x;
+            } else {
+                uint32_t carry = k.carry;
+                if (DELTA) running_sum(v, carry);
+                store_segment(k.p, k.s, lane, v, 0u);
+            }
+        } else if (MODE == kSums && k.valid && lane == 0) {
+            a.ivsum[t] = 0u;
+        }
+        walker_release();
+        h0 = h1;
+        h1 = h2;
+        h2 = h3;
+        c1 = c2;
+    }
+    if (corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
+}
+
+// Data bytes of 8 decode tasks per wave: lanes 8 j .. 8 j + 7 read the 256
+// control bytes of task 8 w + j, 32 each.  The last task of a list writes 0.
+__global__ __launch_bounds__(kThreads) void batch_task_bytes_decode_kernel(BatchArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t total = task_total(a);
+    const uint64_t t = ((uint64_t)blockIdx.x * kWaves + wave) * 8 + lane / 8;
+    const uint32_t part = lane & 7u;
+    uint32_t bytes = 0;
+    bool body = false;
+    if (t < total) {
+        const uint32_t word = a.item_list[t];
+        body = (word & kLastBit) == 0;
+        if (body) {
+            // a segment that is not the last of its list is full, and more
+            // bytes of the list follow its control bytes
+            const uint32_t i = word & ~kLastBit;
+            const uint64_t s = t - a.item_first[t];
+            const uint64_t first = s * kSegCtrl + 32ull * part;
+            const uint8_t *gp = a.in8 + a.in_off[i] + first;
+            const uint32_t sh = (uint32_t)((uintptr_t)gp & 3u);
+            // aligned dwords around the 32 bytes, inside the list's bytes
+            if (first >= sh && first - sh + 36 <= a.in_bytes[i]) {
+                const uint32_t *base = (const uint32_t *)(gp - sh);
+                const uint32_t keep = 0xFFFFFFFFu << (8u * sh);
+                uint32_t codes = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) {
+                    const uint32_t x = (q == 0) ? (base[q] & keep) : base[q];
+                    codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
+                }
+                const uint32_t e = sh ? (base[8] & ~keep) : 0u;
+                codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
+                bytes = 128u + codes;
+            } else {
+                uint32_t c[32];
+#pragma unroll
+                for (uint32_t q = 0; q < 32; ++q) c[q] = gp[q];
+#pragma unroll
+                for (uint32_t q = 0; q < 32; ++q) bytes += control_data_bytes(c[q], 4u);
+            }
+        }
+    }
+    // sum over each group of 8 lanes
+    bytes += __shfl_xor(bytes, 1, kWave);
+    bytes += __shfl_xor(bytes, 2, kWave);
+    bytes += __shfl_xor(bytes, 4, kWave);
+    if (t < total && part == 0) a.ibytes[t] = body ? bytes : 0u;
+}
+
+// ---------------------------------------------------------------- encoding
+
+struct EncTask {
+    bool valid;
+    bool last;
+    uint32_t list;
+    EncodeStream e;
+    uint64_t s;
+    uint64_t boff;
+};
+
+__device__ __forceinline__ EncTask load_enc_task(const BatchArgs &a, uint64_t t, uint64_t t_end) {
+    EncTask k = {};
+    k.valid = t < t_end;
+    if (!k.valid) return k;
+    const uint32_t word = a.item_list[t];
+    const uint32_t first = a.item_first[t];
+    k.list = word & ~kLastBit;
+    k.last = (word & kLastBit) != 0;
+    k.e.in = a.in32 + a.in_off[k.list];
+    k.e.n = a.counts[k.list];
+    k.e.out = a.out8 + a.out_off[k.list];
+    k.e.start = a.starts ? a.starts[k.list] : 0u;
+    k.s = t - first;
+    k.boff = a.ioff[t] - a.ioff[first];
+    return k;
+}
+
+// Data bytes of one encode task per wave (the last task of a list writes 0).
+template <bool DELTA>
+__global__ __launch_bounds__(kThreads) void batch_task_bytes_encode_kernel(BatchArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t total = task_total(a);
+    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wave;
+    if (t >= total) return;
+    const EncTask k = load_enc_task(a, t, total);
+    uint32_t bytes = 0;
+    if (!k.last) {
+        SegValues sv;
+        load_segment_values<DELTA>(k.e, k.s, lane, sv);
+        bytes = segment_data_bytes(sv);
     }
     if (lane == 0) a.ibytes[t] = bytes;
 }
 
-// Sum of the stored differences of every item that is not the last of its list.
-template <uint32_t G>
-__global__ __launch_bounds__(kThreads) void batch_item_sums_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t t = wave_item(wave);
-    const ItemRef r = item_ref(a, t);
-    if (!r.valid) return;
-    uint32_t sum = 0;
-    if (!r.last) {
-        uint8_t *stage = s_stage + wave * kStageBytes;
-        const DecodeArgs p = list_stream(a, r.list);
-        const uint64_t s0 = (uint64_t)r.piece * G;
-        Walker w;
-        walker_begin(p, w, s0, s0 + G, a.ioff[t] - a.ioff[r.first_item], lane);
-#pragma unroll 1
-        for (uint64_t s = s0; s < s0 + G; ++s) {
-            SegPlan seg;
-            uint32_t sh16;
-            walker_step(p, w, stage, lane, seg, sh16);
-            uint32_t v[4][4];
-            extract_segment(p, s, stage, seg, sh16, lane, v);
-            walker_release();
-            uint32_t x = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < 4; ++k) x += v[k][0] + v[k][1] + v[k][2] + v[k][3];
-            sum += wave_last(wave_incl_scan(x));
-        }
-        if (w.corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
-    }
-    if (lane == 0) a.ivsum[t] = sum;
-}
-
-template <uint32_t G, bool DELTA>
-__global__ __launch_bounds__(kThreads) void batch_decode_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t t = wave_item(wave);
-    const ItemRef r = item_ref(a, t);
-    if (!r.valid) return;
-    uint8_t *stage = s_stage + wave * kStageBytes;
-    const DecodeArgs p = list_stream(a, r.list);
-    const uint64_t segs = (p.n + kSegInts - 1) / kSegInts;
-    const uint64_t s0 = (uint64_t)r.piece * G;
-    const uint64_t s_end = s0 + G < segs ? s0 + G : segs;
-    const uint64_t boff = r.piece ? a.ioff[t] - a.ioff[r.first_item] : 0ull;
-    uint32_t carry = 0;
-    if (DELTA) carry = a.starts[r.list] + (r.piece ? a.ivpre[t] - a.ivpre[r.first_item] : 0u);
-    Walker w;
-    walker_begin(p, w, s0, s_end, boff, lane);
-#pragma unroll 1
-    for (uint64_t s = s0; s < s_end; ++s) {
-        SegPlan seg;
-        uint32_t sh16;
-        walker_step(p, w, stage, lane, seg, sh16);
-        uint32_t v[4][4];
-        extract_segment(p, s, stage, seg, sh16, lane, v);
-        walker_release();
-        if (DELTA) running_sum(v, carry);
-        store_segment(p, s, lane, v, 0u);
-    }
-    if (w.corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
-}
-
-template <uint32_t G, bool DELTA>
+template <bool DELTA>
 __global__ __launch_bounds__(kThreads) void batch_encode_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t s_stage[kWaves * kEncStageWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t t = wave_item(wave);
-    const ItemRef r = item_ref(a, t);
-    if (!r.valid) return;
+    const uint32_t total = task_total(a);
+    const uint64_t t0 = ((uint64_t)blockIdx.x * kWaves + wave) * a.chunk;
+    if (t0 >= total) return;
+    const uint64_t t_end = t0 + a.chunk < total ? t0 + a.chunk : total;
     uint32_t *stage = s_stage + wave * kEncStageWords;
-    const EncodeStream e = list_values(a, r.list);
-    const uint64_t segs = (e.n + kSegInts - 1) / kSegInts;
-    const uint64_t s0 = (uint64_t)r.piece * G;
-    const uint64_t s_end = s0 + G < segs ? s0 + G : segs;
-    uint64_t boff = r.piece ? a.ioff[t] - a.ioff[r.first_item] : 0ull;
 #pragma unroll 1
-    for (uint64_t s = s0; s < s_end; ++s) boff += encode_segment<DELTA>(e, s, boff, lane, stage);
-    if (r.last && lane == 0 && a.out_bytes) a.out_bytes[r.list] = (e.n + 3) / 4 + boff;
+    for (uint64_t t = t0; t < t_end; ++t) {
+        const TaskDesc d = a.desc[t];
+        EncodeStream e;
+        e.in = (const uint32_t *)uniform64(d.in);
+        e.n = uniform64(d.n);
+        e.out = (uint8_t *)uniform64(d.out);
+        e.start = uniform32(d.carry);
+        const uint64_t boff = uniform64(d.boff);
+        const uint32_t word = uniform32(d.word);
+        const uint32_t bytes = encode_segment<DELTA>(e, uniform32(d.s), boff, lane, stage);
+        if ((word & kLastBit) && lane == 0 && a.out_bytes) a.out_bytes[word & ~kLastBit] = (e.n + 3) / 4 + boff + bytes;
+    }
 }
 
 uint32_t list_grid(uint32_t m) { return (m + kThreads - 1) / kThreads; }
-uint32_t item_grid(uint32_t t_cap) { return (t_cap + kWaves - 1) / kWaves; }
+uint32_t wave_grid(uint64_t waves) { return (uint32_t)((waves + kWaves - 1) / kWaves); }
 
-template <uint32_t G>
-hipError_t launch_batch_g(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s) {
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s) {
+    const uint64_t chunk_waves = (a.t_cap + a.chunk - 1) / a.chunk;
     switch (phase) {
         case kBatchCount:
-            hipLaunchKernelGGL((batch_count_kernel<G>), dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
+            if (encode)
+                hipLaunchKernelGGL((batch_count_kernel<true>), dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL((batch_count_kernel<false>), dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
+            break;
+        case kBatchMap:
+            hipLaunchKernelGGL(batch_map_kernel, dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
+            break;
+        case kBatchDesc:
+            if (encode)
+                hipLaunchKernelGGL((batch_desc_kernel<true>), dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL((batch_desc_kernel<false>), dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+            break;
+        case kBatchCarries:
+            hipLaunchKernelGGL(batch_carry_kernel, dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
             break;
         case kBatchItemBytes:
             if (!encode)
-                hipLaunchKernelGGL((batch_item_bytes_kernel<G, false, false>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0,
+                hipLaunchKernelGGL(batch_task_bytes_decode_kernel, dim3(wave_grid((a.t_cap + 7) / 8)), dim3(kThreads), 0,
                                    s, a);
             else if (delta)
-                hipLaunchKernelGGL((batch_item_bytes_kernel<G, true, true>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0,
-                                   s, a);
+                hipLaunchKernelGGL((batch_task_bytes_encode_kernel<true>), dim3(wave_grid(a.t_cap)), dim3(kThreads), 0, s,
+                                   a);
             else
-                hipLaunchKernelGGL((batch_item_bytes_kernel<G, true, false>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0,
-                                   s, a);
+                hipLaunchKernelGGL((batch_task_bytes_encode_kernel<false>), dim3(wave_grid(a.t_cap)), dim3(kThreads), 0, s,
+                                   a);
             break;
         case kBatchItemSums:
-            hipLaunchKernelGGL((batch_item_sums_kernel<G>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((batch_walk_kernel<kSums>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
             break;
         case kBatchWork:
             if (encode) {
                 if (delta)
-                    hipLaunchKernelGGL((batch_encode_kernel<G, true>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_encode_kernel<true>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
                 else
-                    hipLaunchKernelGGL((batch_encode_kernel<G, false>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_encode_kernel<false>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
             } else {
                 if (delta)
-                    hipLaunchKernelGGL((batch_decode_kernel<G, true>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_walk_kernel<kDelta>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
                 else
-                    hipLaunchKernelGGL((batch_decode_kernel<G, false>), dim3(item_grid(a.t_cap)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_walk_kernel<kPlain>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
             }
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t launch_batch(const BatchArgs &a, uint32_t item_segs, int phase, bool encode, bool delta, hipStream_t s) {
-    if (phase == kBatchMap) {
-        hipLaunchKernelGGL(batch_map_kernel, dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
-        return hipGetLastError();
-    }
-    switch (item_segs) {
-        case 1: return launch_batch_g<1>(a, phase, encode, delta, s);
-        case 2: return launch_batch_g<2>(a, phase, encode, delta, s);
-        case 4: return launch_batch_g<4>(a, phase, encode, delta, s);
-        case 8: return launch_batch_g<8>(a, phase, encode, delta, s);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 }  // namespace svb

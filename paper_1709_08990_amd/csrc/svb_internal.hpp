@@ -98,7 +98,24 @@ hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uin
                        void *total = nullptr, void *scratch = nullptr);
 hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s);
 
-// Batched calls.  Item = `item_segs` segments of one list = one wave's work.
+// Batched calls.  A task is one 1024-integer segment of one list; each wave of
+// the main pass takes `chunk` consecutive tasks.
+//
+// Per-task descriptor: everything a wave needs to start the task, so that a
+// task costs one 64-byte load before its control bytes can be requested.
+struct alignas(64) TaskDesc {
+    uint64_t in;        // decode: the list's stream; encode: the list's values
+    uint64_t in_bytes;  // decode: bytes readable at `in`
+    uint64_t n;         // integers in the list
+    uint64_t out;       // decode: the list's output (uint32); encode: the list's stream
+    uint64_t boff;      // byte offset of the segment's data in the list's data stream
+    uint32_t s;         // segment index inside the list
+    uint32_t carry;     // delta decode: running sum before the segment; delta encode: start
+    uint32_t word;      // list index, bit 31 set on the list's last segment
+    uint32_t pad[3];
+};
+static_assert(sizeof(TaskDesc) == 64, "one 64-byte descriptor per task");
+
 struct BatchArgs {
     uint32_t m;
     const uint64_t *counts;
@@ -112,17 +129,28 @@ struct BatchArgs {
     uint64_t *out_bytes;       // encode: stream sizes (may be null)
     const uint32_t *starts;    // null: plain
     uint32_t *err;             // decode: corruption / overflow flag (may be null)
-    uint32_t *litems;          // per list: items
-    uint32_t *lbase;           // per list + 1: first item of each list; lbase[m] = items in all
-    uint32_t *item_list;       // per item: its list
-    uint32_t t_cap;            // item capacity of the scratch arrays
-    uint32_t *ibytes;          // per item: data bytes (items that are not the last of their list)
-    uint64_t *ioff;            // per item: exclusive scan of ibytes
-    uint32_t *ivsum;           // per item: sum of stored differences (delta decoding)
-    uint32_t *ivpre;           // per item: exclusive scan of ivsum
+    uint32_t *litems;          // per list: tasks (segments)
+    uint32_t *lbase;           // per list + 1: first task of each list; lbase[m] = tasks in all
+    uint32_t *item_list;       // per task: its list, bit 31 set on a list's last task
+    uint32_t *item_first;      // per task: first task of its list
+    uint32_t t_cap;            // task capacity of the scratch arrays
+    uint32_t chunk;            // tasks per wave in the main pass
+    uint32_t *ibytes;          // per task: data bytes (tasks that are not the last of their list)
+    uint64_t *ioff;            // per task: exclusive scan of ibytes
+    uint32_t *ivsum;           // per task: sum of stored differences (delta decoding)
+    uint32_t *ivpre;           // per task: exclusive scan of ivsum
+    TaskDesc *desc;            // per task
 };
-enum BatchPhase { kBatchCount = 0, kBatchMap = 1, kBatchItemBytes = 2, kBatchItemSums = 3, kBatchWork = 4 };
-hipError_t launch_batch(const BatchArgs &a, uint32_t item_segs, int phase, bool encode, bool delta, hipStream_t s);
+enum BatchPhase {
+    kBatchCount = 0,
+    kBatchMap = 1,
+    kBatchItemBytes = 2,
+    kBatchItemSums = 3,
+    kBatchWork = 4,
+    kBatchDesc = 5,     // descriptors from the byte offsets
+    kBatchCarries = 6   // delta decode: carries from the value sums
+};
+hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s);
 
 // Encoding (persistent, decoupled look-back over tile byte totals).
 uint32_t encode_grid(bool delta, uint32_t num_tiles);

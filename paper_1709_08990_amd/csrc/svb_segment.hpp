@@ -21,10 +21,13 @@ constexpr uint32_t kStageBytes = 4224;
 
 __device__ __forceinline__ bool segment_full(const DecodeArgs &p, uint64_t s) { return (s + 1) * kSegInts <= p.n; }
 
-// Integers of block 64 k + lane of segment s (0..4).
+// Integers of block 64 k + lane of segment s (0..4).  The segment's remaining
+// count is wave-uniform; the per-block part is 32-bit arithmetic.
 __device__ __forceinline__ uint32_t block_ints(const DecodeArgs &p, uint64_t s, uint32_t k, uint32_t lane) {
-    const uint64_t i0 = s * kSegInts + 4ull * (kWave * k + lane);
-    return i0 < p.n ? (uint32_t)((p.n - i0) < 4 ? (p.n - i0) : 4) : 0u;
+    const uint64_t i0 = s * kSegInts;
+    const int32_t rem = i0 >= p.n ? 0 : (int32_t)((p.n - i0) < kSegInts ? (p.n - i0) : kSegInts);
+    const int32_t left = rem - (int32_t)(4u * (kWave * k + lane));
+    return left <= 0 ? 0u : (left >= 4 ? 4u : (uint32_t)left);
 }
 
 // The lane's control bytes of segment s: c[k] is control byte 64 k + lane of
@@ -78,42 +81,54 @@ __device__ __forceinline__ SegPlan plan_segment(const DecodeArgs &p, uint64_t s,
 
 // A segment's data span in flight: up to 5 x 64 chunks of 16 bytes,
 // [abase, abase + 16 nch), where abase is the span start rounded down to 16.
-// Inside the buffer every chunk is one aligned 16-byte load into registers
-// (lane c takes chunks c, c + 64, ...); at the edges of the buffer the chunks
-// are assembled byte by byte when they are staged, bytes outside
+// Lane c takes chunks c, c + 64, ...; a chunk that lies inside the buffer is
+// one aligned 16-byte load, requested by span_load.  A chunk that crosses an
+// edge of the buffer (at most the first and the last of a stream) is marked
+// in `edge` and assembled byte by byte when the span is staged, bytes outside
 // [in, in + in_bytes) reading as 0.
 struct Span {
     const uint8_t *abase;
     uint32_t nch;
-    bool inside;
+    uint32_t edge;  // bit i: chunk lane + 64 i crosses an edge of the buffer
     u32x4a w[5];
 };
 
 __device__ __forceinline__ void span_load(const DecodeArgs &p, Span &sp, uint32_t lane) {
-    sp.inside = sp.abase >= p.in && sp.abase + 16ull * sp.nch <= p.in + p.in_bytes;
-    if (sp.inside) {
+    const uint8_t *hi = p.in + p.in_bytes;
+    sp.edge = 0;
 #pragma unroll
-        for (uint32_t i = 0; i < 5; ++i) {
-            const uint32_t c = lane + kWave * i;
-            if (c < sp.nch) sp.w[i] = *(const u32x4a *)(sp.abase + 16 * c);
+    for (uint32_t i = 0; i < 5; ++i) {
+        const uint32_t c = lane + kWave * i;
+        if (c < sp.nch) {
+            const uint8_t *cp = sp.abase + 16 * c;
+            if (cp >= p.in && cp + 16 <= hi)
+                sp.w[i] = *(const u32x4a *)cp;
+            else
+                sp.edge |= 1u << i;
         }
     }
 }
 
 __device__ __forceinline__ void span_to_lds(const DecodeArgs &p, const Span &sp, uint8_t *stage, uint32_t lane) {
-    if (sp.inside) {
 #pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) {
+        const uint32_t c = lane + kWave * i;
+        if (c < sp.nch && !((sp.edge >> i) & 1u)) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
+    }
+    if (sp.edge) {
+        // all 16 byte loads of a chunk are issued before any is used: one
+        // round trip to memory per edge chunk
+        const uint8_t *hi = p.in + p.in_bytes;
         for (uint32_t i = 0; i < 5; ++i) {
+            if (!((sp.edge >> i) & 1u)) continue;
             const uint32_t c = lane + kWave * i;
-            if (c < sp.nch) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
-        }
-    } else {
-        for (uint32_t c = lane; c < sp.nch; c += kWave) {
+            const uint8_t *cp = sp.abase + 16 * c;
+            uint32_t byte[16];
+#pragma unroll
+            for (uint32_t b = 0; b < 16; ++b) byte[b] = (cp + b >= p.in && cp + b < hi) ? (uint32_t)cp[b] : 0u;
             uint32_t d[4] = {0u, 0u, 0u, 0u};
-            for (uint32_t b = 0; b < 16; ++b) {
-                const uint8_t *a = sp.abase + 16 * c + b;
-                if (a >= p.in && a < p.in + p.in_bytes) d[b >> 2] |= (uint32_t)*a << (8 * (b & 3));
-            }
+#pragma unroll
+            for (uint32_t b = 0; b < 16; ++b) d[b >> 2] |= byte[b] << (8 * (b & 3));
             *(u32x4a *)(stage + kStagePad + 16 * c) = u32x4a{d[0], d[1], d[2], d[3]};
         }
     }
@@ -242,12 +257,19 @@ __device__ __forceinline__ void store_segment(const DecodeArgs &p, uint64_t s, u
             __builtin_nontemporal_store(u32x4{v[k][0] + add, v[k][1] + add, v[k][2] + add, v[k][3] + add},
                                         (u32x4 *)(o + 4 * kWave * k));
     } else {
+        // whole blocks of a partial segment still take one 16-byte store
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
             const uint32_t m = block_ints(p, s, k, lane);
+            uint32_t *ok = o + 4 * kWave * k;
+            if (m == 4) {
+                __builtin_nontemporal_store(u32x4{v[k][0] + add, v[k][1] + add, v[k][2] + add, v[k][3] + add},
+                                            (u32x4 *)ok);
+            } else {
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j)
-                if (j < m) o[4 * kWave * k + j] = v[k][j] + add;
+                for (uint32_t j = 0; j < 3; ++j)
+                    if (j < m) ok[j] = v[k][j] + add;
+            }
         }
     }
 }
@@ -283,10 +305,14 @@ __device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t 
     }
     const uint32_t last_r = (n & 3) ? (uint32_t)(n & 3) : 4u;
     const uint64_t b0 = first + (uint64_t)P * lane;
+    uint32_t c[P];
+#pragma unroll
+    for (uint32_t i = 0; i < P; ++i) c[i] = (b0 + i < nblocks) ? (uint32_t)in[b0 + i] : 0u;
     uint32_t bytes = 0;
+#pragma unroll
     for (uint32_t i = 0; i < P; ++i) {
         const uint64_t b = b0 + i;
-        if (b < nblocks) bytes += control_data_bytes(in[b], (b == nblocks - 1) ? last_r : 4u);
+        if (b < nblocks) bytes += control_data_bytes(c[i], (b == nblocks - 1) ? last_r : 4u);
     }
     return bytes;
 }

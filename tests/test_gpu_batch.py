@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 svb = pytest.importorskip("paper_1709_08990_amd")
 
-ITEM_SEGS = [1, 2, 4, 8]
+CHUNKS = [1, 2, 4, 8, 16]
 EDGE_SIZES = [0, 1, 3, 4, 5, 63, 64, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
               16385, 40000, 100003]
 SENTINEL32 = 0x5EEDF00D
@@ -26,7 +26,7 @@ def _device():
     yield
     torch.cuda.synchronize()
     for kind in range(4):
-        svb.svb_set_batch_item_segments(kind, 2)
+        svb.svb_set_batch_chunk(kind, 4)
 
 
 def dev_u64(a):
@@ -125,23 +125,23 @@ def check_batch(lists, starts, seed, tag):
 
 
 @pytest.mark.parametrize("delta", [False, True])
-@pytest.mark.parametrize("item_segs", ITEM_SEGS)
-def test_batch_edge_sizes(item_segs, delta):
+@pytest.mark.parametrize("chunk", CHUNKS)
+def test_batch_edge_sizes(chunk, delta):
     for kind in range(4):
-        svb.svb_set_batch_item_segments(kind, item_segs)
-    lists, starts = make_lists(EDGE_SIZES, seed=11 + item_segs, delta=delta)
-    check_batch(lists, starts, seed=5 + item_segs, tag="edges G=%d" % item_segs)
+        svb.svb_set_batch_chunk(kind, chunk)
+    lists, starts = make_lists(EDGE_SIZES, seed=11 + chunk, delta=delta)
+    check_batch(lists, starts, seed=5 + chunk, tag="edges chunk=%d" % chunk)
 
 
 @pytest.mark.parametrize("delta", [False, True])
 def test_batch_many_small_lists(delta):
-    """More than 65536 items, so the item scans take the multi-workgroup path."""
+    """More than 65536 lists and tasks, so the scans take the multi-workgroup path."""
     rng = np.random.default_rng(21)
     sizes = rng.integers(0, 48, size=70_000)
     sizes[::9_973] = rng.integers(9_000, 30_000, size=sizes[::9_973].size)
     lists, starts = make_lists(sizes, seed=22, delta=delta)
     for kind in range(4):
-        svb.svb_set_batch_item_segments(kind, 1)
+        svb.svb_set_batch_chunk(kind, 16)
     check_batch(lists, starts, seed=23, tag="many")
 
 
@@ -194,7 +194,7 @@ def test_batch_autotune_then_decode():
               dev_u64(out_off), out, to_dev_u32(starts), int(counts.sum()))
     log_case("batch autotune")
     g = svb.svb_autotune_decode_batch(*d_args)
-    assert g in ITEM_SEGS
+    assert g in CHUNKS
     out.zero_()
     svb.svb_decode_batch(*d_args)
     torch.cuda.synchronize()
