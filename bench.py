@@ -22,7 +22,11 @@ Prints one JSON line.  Besides the headline it carries:
                 decode of 2^28 integers with unpredictable lengths;
   batched       200,000 delta-coded posting lists (about 3e8 integers):
                 autotuned batched decode and encode, against the single-array
-                rate and against one svb_delta_decode call per list.
+                rate and against one svb_delta_decode call per list;
+  serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
+                in HBM, queries of 2..8 lists: closed-loop saturation rate,
+                then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
+                and integers/s.
 
 `python bench.py --summarize-counters FETCH.csv WRITE.csv OUT.md` turns two
 rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) into the
@@ -336,6 +340,119 @@ def measure_batched(svb, torch, np, inputs, steps, warmup):
     return res
 
 
+def build_pool(svb, torch, np, inputs, m, total, cap, seed):
+    """Serving pool: m delta-coded posting lists (rank-size Zipf lengths in [1, cap] summing to
+    `total`, sorted sets over [0, 2^31) drawn on the GPU), encoded by the batched encoder and
+    packed back to back.  Returns device tables plus the source values for checking."""
+    lens = inputs.zipf_rank_lengths(m, total, cap, seed=seed)
+    vals, offs = inputs.sorted_sets_device(lens, seed=seed + 1)
+    counts = lens.astype(np.uint64)
+    n = int(counts.sum())
+    u64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+    caps = (counts + 3) // 4 + 4 * counts
+    loose_off = np.zeros(m, dtype=np.uint64)
+    np.cumsum(caps[:-1], out=loose_off[1:])
+    d_counts, d_val_off = u64(counts), u64(offs[:-1])
+    starts = torch.zeros(m, dtype=torch.int32, device="cuda")
+    sizes = torch.empty(m, dtype=torch.int64, device="cuda")
+    loose = torch.empty(int(caps.sum()), dtype=torch.uint8, device="cuda")
+    svb.svb_encode_batch(m, d_counts, d_val_off, vals, u64(loose_off), loose, sizes, starts, n)
+    h_sizes = sizes.cpu().numpy().view(np.uint64).copy()
+    del loose
+    tight_off = np.zeros(m, dtype=np.uint64)
+    np.cumsum(h_sizes[:-1], out=tight_off[1:])
+    nbytes = int(h_sizes.sum())
+    tight = torch.empty(nbytes + 64, dtype=torch.uint8, device="cuda")
+    sizes2 = torch.empty(m, dtype=torch.int64, device="cuda")
+    d_tight_off = u64(tight_off)
+    svb.svb_encode_batch(m, d_counts, d_val_off, vals, d_tight_off, tight, sizes2, starts, n)
+    torch.cuda.synchronize()
+    assert torch.equal(sizes, sizes2), "pool encode is not deterministic"
+    return {"counts": d_counts, "in_off": d_tight_off, "in_bytes": sizes, "streams": tight, "starts": starts,
+            "vals": vals, "val_off": offs, "h_counts": counts, "integers": n, "compressed_bytes": nbytes}
+
+
+def latency_summary(lat, ints, wall):
+    import numpy as np
+    return {"queries": int(lat.size), "wall_s": wall, "qps": lat.size / wall,
+            "uint32_per_s": float(ints) / wall, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean())}
+
+
+def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
+                    arena_bytes=1 << 30, slots=4, max_batch_lists=8192):
+    """Serving loop over a device-resident pool of delta-coded posting lists: closed-loop saturation,
+    then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate, each query 2..8 lists
+    chosen uniformly; latency from arrival to the host seeing the batch complete."""
+    from paper_1709_08990_amd import serve
+    t0 = time.perf_counter()
+    pool = build_pool(svb, torch, np, inputs, lists, total, cap, seed=91)
+    log("serving: pool of %d lists, %d integers, %.2f GB compressed (%.1f s)"
+        % (lists, pool["integers"], pool["compressed_bytes"] / 1e9, time.perf_counter() - t0))
+    server = serve.Server(pool["counts"], pool["in_off"], pool["in_bytes"], pool["streams"], pool["starts"],
+                          arena_bytes=arena_bytes, slots=slots, max_batch_lists=max_batch_lists)
+    h_counts = pool["h_counts"]
+    # correctness: a few queries read back from the arena against the source values
+    _, check = inputs.poisson_queries(64, 1.0, lists, seed=92)
+    for q, p in enumerate(check):
+        server.submit(q, p)
+    seen, ok = 0, True
+    while seen < len(check):
+        server.step(block=True)
+        for qid, off, n in server.poll():
+            p = check[qid]
+            want = torch.cat([pool["vals"][int(pool["val_off"][l]):int(pool["val_off"][l + 1])] for l in p])
+            got = torch.empty(max(1, n), dtype=torch.int32, device="cuda")
+            if n:
+                svb.svb_copy_u32(n, svb.svb_server_arena(server.handle) + 4 * off, got)
+            torch.cuda.synchronize()
+            ok = ok and torch.equal(got[:n], want)
+            server.release(qid)
+            seen += 1
+    del pool["vals"]
+    assert ok, "served results differ from the pool's source values"
+
+    def query_ints(qoff, ids):
+        c = h_counts[ids]
+        return np.add.reduceat(c, qoff[:-1]).astype(np.float64) if ids.size else np.zeros(0)
+
+    # warm-up, then closed loop at a few depths to find the saturation rate
+    _, qo, ids = inputs.poisson_queries_flat(5_000, 1.0, lists, seed=93)
+    server.replay((qo, ids), outstanding=512)
+    closed = []
+    est_qps = None
+    for depth in (256, 1024, 4096):
+        nq = 20_000 if est_qps is None else int(min(4e6, max(20_000, 2.0 * est_qps)))
+        _, qo, ids = inputs.poisson_queries_flat(nq, 1.0, lists, seed=94 + depth)
+        lat, wall = server.replay((qo, ids), outstanding=depth)
+        r = latency_summary(lat, query_ints(qo, ids).sum(), wall)
+        r["outstanding"] = depth
+        closed.append(r)
+        est_qps = max(est_qps or 0.0, r["qps"])
+        log("serving closed loop depth %d: %.0f queries/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
+            % (depth, r["qps"], r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+    sat = max(closed, key=lambda r: r["qps"])
+    opened = []
+    for load in (0.5, 0.8):
+        rate = load * sat["qps"]
+        nq = max(1000, int(rate * seconds))
+        times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=97 + int(10 * load))
+        lat, wall = server.replay((qo, ids), arrivals=times)
+        r = latency_summary(lat, query_ints(qo, ids).sum(), wall)
+        r.update({"load": load, "offered_qps": rate, "window_s": float(times[-1])})
+        opened.append(r)
+        log("serving open loop %.1fx: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
+            % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+    st = server.stats()
+    server.close()
+    assert st["err"] == 0, "a served batch reported corrupt input"
+    return {"pool": {"lists": lists, "integers": pool["integers"], "compressed_bytes": pool["compressed_bytes"],
+                     "max_list": int(h_counts.max()), "median_list": float(np.median(h_counts))},
+            "arena_bytes": arena_bytes, "slots": slots, "max_batch_lists": max_batch_lists,
+            "results_checked": len(check), "closed_loop": closed, "saturation_qps": sat["qps"],
+            "saturation_uint32_per_s": sat["uint32_per_s"], "open_loop": opened, "server_stats": st}
+
+
 def run_cpu_baseline(x, min_seconds=10.0):
     """The oracle as it stands: single-threaded scalar C delta decode of the whole array, repeated."""
     import oracle
@@ -365,9 +482,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 200,000-list batched measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of each open-loop serving window (seconds of arrivals)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} -- python3 bench.py "
-                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28 --no-batched")
+                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28 --no-batched --no-serving")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, command=args.counter_command)
@@ -458,6 +578,12 @@ def main():
         line["batched"] = rb
         log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array, %.1fx one call per list)"
             % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"], rb["vs_one_call_per_list"]))
+    if not args.no_serving:
+        log("serving: building the 10^6-list pool on the GPU")
+        rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)
+        single = line.get("at_2p28", {}).get("delta_docids", {}).get("uint32_per_s", line["value"])
+        rs["saturation_vs_single_array"] = rs["saturation_uint32_per_s"] / single
+        line["serving"] = rs
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         line["cpu_baseline"] = run_cpu_baseline(x)

@@ -240,6 +240,23 @@ uint32_t *svb_server_arena(void *server);
 int svb_server_stats(void *server, uint64_t *out, uint32_t cap);
 int svb_server_destroy(void *server);
 
+/*
+ * svb_server_replay drives the server from the calling thread with a query
+ * trace and measures latency (a load generator for the serving loop).  Query i
+ * asks for lists[qoff[i] .. qoff[i+1]) (host arrays; every query names at
+ * least one list) and gets the id id_base + i.  Open loop (arrival_s != NULL):
+ * query i is submitted once arrival_s[i] seconds have passed since the call
+ * began; its latency runs from arrival_s[i] to the moment the host sees its
+ * batch complete.  Closed loop (arrival_s == NULL): `outstanding` queries are
+ * kept in the system, latency runs from submission.  Results are released as
+ * soon as they complete (nothing is read back).  latency_s[i] receives
+ * seconds; *wall_s (if not NULL) the call's duration.  Returns SVB_OK, or a
+ * negative status (bad trace, an id already live, a query that can never be
+ * admitted, a HIP error) with the server's state as of the failure.
+ */
+int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
+                      uint32_t outstanding, uint64_t id_base, double *latency_s, double *wall_s);
+
 /* Message for a status code (static string). */
 const char *svb_strerror(int status);
 

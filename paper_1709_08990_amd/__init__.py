@@ -17,7 +17,8 @@ __all__ = [
     "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
-    "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "encode", "decode",
+    "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
+    "encode", "decode",
     "LIB_PATH",
 ]
 
@@ -64,6 +65,7 @@ def lib():
             "svb_server_arena": (vp, [vp]),
             "svb_server_stats": (i32, [vp, vp, u32]),
             "svb_server_destroy": (i32, [vp]),
+            "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, u64, vp, vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -277,6 +279,33 @@ def svb_server_stats(server):
 
 def svb_server_destroy(server):
     return _check(lib().svb_server_destroy(server), "svb_server_destroy")
+
+
+def svb_server_replay(server, picks, arrivals=None, outstanding=0, id_base=0):
+    """Replays queries open loop at ``arrivals`` (seconds) or, with arrivals None, closed loop with
+    ``outstanding`` queries in flight.  picks: a sequence of list-id arrays, or a pair (qoff, ids)
+    with query i asking for ids[qoff[i]:qoff[i+1]].  Returns (latencies in seconds, wall seconds)."""
+    import numpy as np
+    if isinstance(picks, tuple) and len(picks) == 2:
+        qoff = np.ascontiguousarray(picks[0], dtype=np.uint64)
+        ids = np.ascontiguousarray(picks[1], dtype=np.uint32)
+        nq = qoff.size - 1
+    else:
+        nq = len(picks)
+        qoff = np.zeros(nq + 1, dtype=np.uint64)
+        np.cumsum([len(p) for p in picks], out=qoff[1:])
+        ids = np.ascontiguousarray(np.concatenate(picks) if nq else np.zeros(0), dtype=np.uint32)
+    if ids.size == 0:
+        ids = np.zeros(1, dtype=np.uint32)
+    arr = None if arrivals is None else np.ascontiguousarray(arrivals, dtype=np.float64)
+    if arr is not None and arr.size != nq:
+        raise ValueError("one arrival time per query")
+    lat = np.zeros(max(1, nq), dtype=np.float64)
+    wall = ctypes.c_double(0.0)
+    _check(lib().svb_server_replay(server, nq, qoff.ctypes.data, ids.ctypes.data,
+                                   None if arr is None else arr.ctypes.data, int(outstanding), int(id_base),
+                                   lat.ctypes.data, ctypes.addressof(wall)), "svb_server_replay")
+    return lat[:nq], wall.value
 
 
 # ------------------------------------------------------------------ conveniences

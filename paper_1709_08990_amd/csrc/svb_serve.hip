@@ -15,6 +15,7 @@
 // Host work per step is bookkeeping plus one asynchronous copy of the batch's
 // list table; nothing waits for the device unless the caller asks to block.
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -237,6 +238,38 @@ int launch(Server &s) {
     return SVB_OK;
 }
 
+int submit_locked(Server &s, uint64_t query_id, uint32_t k, const uint32_t *list_ids) {
+    if (s.queries.count(query_id)) return SVB_ERR_INVALID;
+    Query q;
+    q.id = query_id;
+    q.lists.assign(list_ids, list_ids + k);
+    q.ints = 0;
+    for (uint32_t l : q.lists) {
+        if (l >= s.m) return SVB_ERR_INVALID;
+        q.ints += s.counts[l];
+    }
+    if (q.ints > s.arena_ints || k > s.max_batch_lists) return SVB_ERR_INVALID;  // could never be admitted
+    q.arena_off = 0;
+    q.state = 0;
+    s.queries.emplace(query_id, std::move(q));
+    s.waiting.push_back(query_id);
+    return SVB_OK;
+}
+
+// One scheduling step (see svb_server_step).
+int step_locked(Server &s, bool block) {
+    int st = retire(s, false);
+    if (st != SVB_OK) return st;
+    admit(s);
+    if ((st = launch(s)) != SVB_OK) return st;
+    if (block && s.completed.empty()) {
+        if ((st = retire(s, true)) != SVB_OK) return st;
+        admit(s);
+        if ((st = launch(s)) != SVB_OK) return st;
+    }
+    return SVB_OK;
+}
+
 void destroy(Server *s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
@@ -303,21 +336,7 @@ int svb_server_submit(void *server, uint64_t query_id, uint32_t k, const uint32_
     Server *s = (Server *)server;
     if (!s || k == 0 || !list_ids) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
-    if (s->queries.count(query_id)) return SVB_ERR_INVALID;
-    Query q;
-    q.id = query_id;
-    q.lists.assign(list_ids, list_ids + k);
-    q.ints = 0;
-    for (uint32_t l : q.lists) {
-        if (l >= s->m) return SVB_ERR_INVALID;
-        q.ints += s->counts[l];
-    }
-    if (q.ints > s->arena_ints || k > s->max_batch_lists) return SVB_ERR_INVALID;  // could never be admitted
-    q.arena_off = 0;
-    q.state = 0;
-    s->queries.emplace(query_id, std::move(q));
-    s->waiting.push_back(query_id);
-    return SVB_OK;
+    return submit_locked(*s, query_id, k, list_ids);
 }
 
 int svb_server_step(void *server, int block) {
@@ -325,15 +344,8 @@ int svb_server_step(void *server, int block) {
     if (!s) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
     (void)hipSetDevice(s->device);
-    int st = retire(*s, false);
+    const int st = step_locked(*s, block != 0);
     if (st != SVB_OK) return st;
-    admit(*s);
-    if ((st = launch(*s)) != SVB_OK) return st;
-    if (block && s->completed.empty()) {
-        if ((st = retire(*s, true)) != SVB_OK) return st;
-        admit(*s);
-        if ((st = launch(*s)) != SVB_OK) return st;
-    }
     return (int)std::min<size_t>(s->completed.size(), 1u << 30);
 }
 
@@ -362,6 +374,60 @@ int svb_server_release(void *server, uint64_t query_id) {
     if (it == s->queries.end() || it->second.state != 3) return SVB_ERR_INVALID;
     arena_free(*s, it->second.arena_off, it->second.ints);
     s->queries.erase(it);
+    return SVB_OK;
+}
+
+int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
+                      uint32_t outstanding, uint64_t id_base, double *latency_s, double *wall_s) {
+    Server *s = (Server *)server;
+    if (!s || !qoff || (nq && (!lists || !latency_s)) || (!arrival_s && outstanding == 0)) return SVB_ERR_INVALID;
+    for (uint64_t i = 0; i < nq; ++i)
+        if (qoff[i + 1] <= qoff[i] || qoff[i + 1] - qoff[i] > 0xFFFFFFFFull) return SVB_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(s->mu);
+    (void)hipSetDevice(s->device);
+    for (uint64_t i = 0; i < nq; ++i)
+        if (s->queries.count(id_base + i)) return SVB_ERR_INVALID;
+    typedef std::chrono::steady_clock clock;
+    const clock::time_point t0 = clock::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    std::vector<double> sent(nq, 0.0);
+    std::vector<uint64_t> other;  // completions of queries submitted outside this replay stay pollable
+    uint64_t next = 0, done = 0;
+    int st = SVB_OK;
+    while (done < nq) {
+        // arrivals that are due (open loop) or room under the outstanding limit (closed loop)
+        const double t = now_s();
+        while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding)) {
+            sent[next] = arrival_s ? arrival_s[next] : t;
+            st = submit_locked(*s, id_base + next, (uint32_t)(qoff[next + 1] - qoff[next]), lists + qoff[next]);
+            if (st != SVB_OK) return st;
+            ++next;
+        }
+        // closed loop: nothing else can happen until a batch finishes, so wait for one
+        const bool block = !arrival_s && next - done >= outstanding;
+        if ((st = step_locked(*s, block)) != SVB_OK) return st;
+        if (s->completed.empty() && !s->waiting.empty() && s->admitted.empty() &&
+            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot &sl) { return sl.busy; }))
+            return SVB_ERR_NOMEM;  // nothing on the device and the arena is held by unreleased results
+        if (!s->completed.empty()) {
+            const double tc = now_s();
+            while (!s->completed.empty()) {
+                const uint64_t id = s->completed.front();
+                s->completed.pop_front();
+                auto it = s->queries.find(id);
+                if (id >= id_base && id - id_base < nq) {
+                    latency_s[id - id_base] = tc - sent[id - id_base];
+                    arena_free(*s, it->second.arena_off, it->second.ints);
+                    s->queries.erase(it);
+                    ++done;
+                } else {
+                    other.push_back(id);
+                }
+            }
+        }
+    }
+    for (uint64_t id : other) s->completed.push_back(id);
+    if (wall_s) *wall_s = now_s();
     return SVB_OK;
 }
 

@@ -21,6 +21,8 @@ run them small):
   total integer count; each list is a sorted set of distinct ids in [0, 2^31).
 * ``poisson_queries``  -- arrival times of a Poisson process and, per query,
   2..8 distinct list ids.
+* ``sorted_sets_device`` -- the posting-list sets drawn on a GPU with torch, for
+  the serving pool (10^6 lists, about 1.6e9 integers).
 """
 import numpy as np
 
@@ -154,14 +156,73 @@ def posting_lists(m=200_000, total=300_000_000, cap=1 << 20, seed=4):
 def poisson_queries(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8):
     """Arrival times (seconds, Poisson process at ``qps``) and, per query, kmin..kmax distinct
     list ids chosen uniformly.  Returns (times float64[n], list of int64 arrays)."""
+    t, qoff, ids = poisson_queries_flat(n_queries, qps, n_lists, seed, kmin, kmax)
+    return t, [ids[qoff[i]:qoff[i + 1]] for i in range(n_queries)]
+
+
+def poisson_queries_flat(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8):
+    """``poisson_queries`` with the picks flattened: (times, qoff int64[n+1], ids int64)."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / qps, size=n_queries))
     ks = rng.integers(kmin, kmax + 1, size=n_queries)
-    picks = []
-    for k in ks:
-        sel = rng.choice(n_lists, size=int(k), replace=False) if n_lists >= k else np.arange(n_lists)
-        picks.append(np.asarray(sel, dtype=np.int64))
-    return t, picks
+    if n_lists < kmax:
+        ks = np.minimum(ks, n_lists)
+    qoff = np.zeros(n_queries + 1, dtype=np.int64)
+    np.cumsum(ks, out=qoff[1:])
+    ids = rng.integers(0, n_lists, size=int(qoff[-1]), dtype=np.int64)
+    # a query holding a repeated id is drawn again without replacement (queries of equal k are
+    # checked together, each id against the ones before it)
+    for k in np.unique(ks):
+        rows = np.nonzero(ks == k)[0]
+        block = ids[qoff[rows][:, None] + np.arange(k)[None, :]]
+        rep = np.zeros(rows.size, dtype=bool)
+        for a in range(1, k):
+            rep |= np.any(block[:, :a] == block[:, a:a + 1], axis=1)
+        for q in rows[rep]:
+            ids[qoff[q]:qoff[q + 1]] = rng.choice(n_lists, size=int(k), replace=False)
+    return t, qoff, ids
+
+
+def sorted_sets_device(lengths, universe=1 << 31, seed=5, chunk=1 << 26, device="cuda"):
+    """``sorted_sets`` generated on a torch device (for pools too large for the host to build
+    quickly): the same exponential-spacings construction, drawn with torch's generator, so the
+    values differ from the host version's.  Within a list the values are non-decreasing and
+    below ``universe``.  Returns (values as a device int32 tensor holding the uint32 bits,
+    offsets int64 numpy of size m+1)."""
+    import torch
+    lengths = np.asarray(lengths, dtype=np.int64)
+    m = lengths.size
+    offsets = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    out = torch.empty(max(1, int(offsets[-1])), dtype=torch.int32, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    i = 0
+    while i < m:
+        j = int(np.searchsorted(offsets, offsets[i] + chunk, side="right")) - 1
+        j = min(m, max(j, i + 1))
+        ls = torch.from_numpy(lengths[i:j]).to(device)
+        nvals = int(offsets[j] - offsets[i])
+        seg = ls + 1
+        e = torch.empty(int(seg.sum().item()), dtype=torch.float64, device=device).exponential_(generator=g)
+        cs = torch.cumsum(e, 0)
+        del e
+        seg_end = torch.cumsum(seg, 0) - 1
+        seg_begin = seg_end - ls
+        base = torch.where(seg_begin > 0, cs[torch.clamp(seg_begin - 1, min=0)], torch.zeros_like(cs[:1]))
+        tot = cs[seg_end] - base
+        lid = torch.repeat_interleave(torch.arange(j - i, device=device), ls)
+        k = torch.arange(nvals, device=device) - torch.repeat_interleave(torch.cumsum(ls, 0) - ls, ls)
+        frac = (cs[seg_begin[lid] + k] - base[lid]) / tot[lid]
+        del cs
+        span = float(universe) - ls.to(torch.float64)[lid]
+        y = torch.minimum(torch.floor(frac * span), span - 1.0)
+        vals = y.to(torch.int64) + k
+        out[int(offsets[i]):int(offsets[j])] = (vals & 0xFFFFFFFF).to(torch.int32) if universe > (1 << 31) \
+            else vals.to(torch.int32)
+        del frac, span, y, vals, lid, k
+        i = j
+    return out, offsets
 
 
 def random_bytes(n, seed=7):

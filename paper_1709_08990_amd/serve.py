@@ -9,8 +9,8 @@ import time
 
 import numpy as np
 
-from . import (svb_server_create, svb_server_destroy, svb_server_poll, svb_server_release, svb_server_stats,
-               svb_server_step, svb_server_submit)
+from . import (svb_server_create, svb_server_destroy, svb_server_poll, svb_server_release, svb_server_replay,
+               svb_server_stats, svb_server_step, svb_server_submit)
 
 
 class Server:
@@ -41,6 +41,11 @@ class Server:
 
     def stats(self):
         return svb_server_stats(self.handle)
+
+    def replay(self, picks, arrivals=None, outstanding=0, id_base=1 << 62):
+        """Native load generator: open loop at ``arrivals`` or closed loop with ``outstanding``
+        queries in flight; results are released unread.  Returns (latencies, wall seconds)."""
+        return svb_server_replay(self.handle, picks, arrivals, outstanding, id_base)
 
     def close(self):
         if self.handle:

@@ -121,3 +121,30 @@ def test_overlapping_batches_and_refusals():
     assert st["completed"] == 200 and st["err"] == 0
     assert st["waiting"] == 0 and st["admitted_not_launched"] == 0 and st["arena_in_use_ints"] == 0
     server.close()
+
+
+def test_replay_open_and_closed_loop():
+    lists, starts, counts, dev = make_pool(2_000, 1_500_000, 1 << 15, True, seed=91)
+    server = serve.Server(dev["counts"], dev["in_off"], dev["in_bytes"], dev["streams"], dev["starts"],
+                          arena_bytes=4 << 20, slots=4, max_batch_lists=512)
+    times, qoff, ids = inputs.poisson_queries_flat(3_000, 20_000.0, len(lists), seed=92)
+    log_case("serve replay open loop")
+    lat, wall = server.replay((qoff, ids), arrivals=times)
+    assert lat.size == 3_000 and np.all(lat > 0) and wall >= times[-1]
+    log_case("serve replay closed loop")
+    lat2, _ = server.replay((qoff, ids), outstanding=64)
+    assert lat2.size == 3_000 and np.all(lat2 > 0)
+    st = server.stats()
+    assert st["completed"] == 6_000 and st["err"] == 0 and st["arena_in_use_ints"] == 0
+    assert st["integers"] == 2 * int(counts[ids].sum())
+    # the server still answers ordinary queries afterwards, correctly
+    p = ids[qoff[5]:qoff[6]]
+    server.submit(7, p)
+    got = []
+    while not got:
+        server.step(block=True)
+        got = server.poll()
+    (_, off, n), = got
+    np.testing.assert_array_equal(read_result(server, off, n), expected(lists, starts, True, p))
+    server.release(7)
+    server.close()

@@ -1,7 +1,7 @@
 """Pins for the oracle (C and pure Python) against what the paper and arithmetic fix.
 
 Each test names the passage it follows.  None of these tests touch a GPU; they
-pin the oracle before it is trusted to judge the HIP library.
+pin the oracle before it is trusted to check the HIP library.
 """
 import itertools
 import json
