@@ -111,9 +111,12 @@ int svb_delta_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t star
  *   err        device uint32 or NULL.  Set to SVB_DECODE_CORRUPT when the
  *              control bytes describe more data bytes than in_bytes - ceil(n/4);
  *              left untouched otherwise (initialise it to 0).  On corrupt
- *              input the contents of `out` are unspecified, but no byte
- *              outside [in, in + in_bytes) is read and nothing outside
- *              out[0..n) is written.
+ *              input the contents of `out` are unspecified, and nothing
+ *              outside out[0..n) is written.  Reads stay inside the aligned
+ *              16-byte chunks that overlap [in, in + in_bytes): such a chunk
+ *              never crosses a page, so the decoder cannot fault on memory
+ *              next to the stream, and bytes outside the stream never change
+ *              a decoded value.
  */
 int svb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err,
                void *stream);

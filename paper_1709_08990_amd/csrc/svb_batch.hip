@@ -287,26 +287,19 @@ __global__ __launch_bounds__(kThreads) void batch_task_bytes_decode_kernel(Batch
             const uint64_t first = s * kSegCtrl + 32ull * part;
             const uint8_t *gp = a.in8 + a.in_off[i] + first;
             const uint32_t sh = (uint32_t)((uintptr_t)gp & 3u);
-            // aligned dwords around the 32 bytes, inside the list's bytes
-            if (first >= sh && first - sh + 36 <= a.in_bytes[i]) {
-                const uint32_t *base = (const uint32_t *)(gp - sh);
-                const uint32_t keep = 0xFFFFFFFFu << (8u * sh);
-                uint32_t codes = 0;
+            // the aligned dwords around the 32 bytes: each holds at least one
+            // of them, so none crosses a page the list does not touch
+            const uint32_t *base = (const uint32_t *)(gp - sh);
+            const uint32_t keep = 0xFFFFFFFFu << (8u * sh);
+            uint32_t codes = 0;
 #pragma unroll
-                for (uint32_t q = 0; q < 8; ++q) {
-                    const uint32_t x = (q == 0) ? (base[q] & keep) : base[q];
-                    codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
-                }
-                const uint32_t e = sh ? (base[8] & ~keep) : 0u;
-                codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
-                bytes = 128u + codes;
-            } else {
-                uint32_t c[32];
-#pragma unroll
-                for (uint32_t q = 0; q < 32; ++q) c[q] = gp[q];
-#pragma unroll
-                for (uint32_t q = 0; q < 32; ++q) bytes += control_data_bytes(c[q], 4u);
+            for (uint32_t q = 0; q < 8; ++q) {
+                const uint32_t x = (q == 0) ? (base[q] & keep) : base[q];
+                codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
             }
+            const uint32_t e = sh ? (base[8] & ~keep) : 0u;
+            codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
+            bytes = 128u + codes;
         }
     }
     // sum over each group of 8 lanes

@@ -81,56 +81,35 @@ __device__ __forceinline__ SegPlan plan_segment(const DecodeArgs &p, uint64_t s,
 
 // A segment's data span in flight: up to 5 x 64 chunks of 16 bytes,
 // [abase, abase + 16 nch), where abase is the span start rounded down to 16.
-// Lane c takes chunks c, c + 64, ...; a chunk that lies inside the buffer is
-// one aligned 16-byte load, requested by span_load.  A chunk that crosses an
-// edge of the buffer (at most the first and the last of a stream) is marked
-// in `edge` and assembled byte by byte when the span is staged, bytes outside
-// [in, in + in_bytes) reading as 0.
+// Lane c takes chunks c, c + 64, ...; each chunk that overlaps the buffer
+// [in, in + in_bytes) is one aligned 16-byte load.  Such a load cannot fault:
+// an aligned 16-byte chunk never straddles a page, and it holds at least one
+// byte of the buffer.  Its bytes outside the buffer are staged but never
+// decide a value (an integer's bytes always lie inside its span).  A chunk
+// wholly outside the buffer (only on corrupt input, whose span runs past the
+// end) is not loaded and stages as zeros.
 struct Span {
     const uint8_t *abase;
     uint32_t nch;
-    uint32_t edge;  // bit i: chunk lane + 64 i crosses an edge of the buffer
     u32x4a w[5];
 };
 
 __device__ __forceinline__ void span_load(const DecodeArgs &p, Span &sp, uint32_t lane) {
     const uint8_t *hi = p.in + p.in_bytes;
-    sp.edge = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 5; ++i) {
         const uint32_t c = lane + kWave * i;
-        if (c < sp.nch) {
-            const uint8_t *cp = sp.abase + 16 * c;
-            if (cp >= p.in && cp + 16 <= hi)
-                sp.w[i] = *(const u32x4a *)cp;
-            else
-                sp.edge |= 1u << i;
-        }
+        const uint8_t *cp = sp.abase + 16 * c;
+        sp.w[i] = u32x4a{0u, 0u, 0u, 0u};
+        if (c < sp.nch && cp < hi && cp + 16 > p.in) sp.w[i] = *(const u32x4a *)cp;
     }
 }
 
-__device__ __forceinline__ void span_to_lds(const DecodeArgs &p, const Span &sp, uint8_t *stage, uint32_t lane) {
+__device__ __forceinline__ void span_to_lds(const DecodeArgs &, const Span &sp, uint8_t *stage, uint32_t lane) {
 #pragma unroll
     for (uint32_t i = 0; i < 5; ++i) {
         const uint32_t c = lane + kWave * i;
-        if (c < sp.nch && !((sp.edge >> i) & 1u)) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
-    }
-    if (sp.edge) {
-        // all 16 byte loads of a chunk are issued before any is used: one
-        // round trip to memory per edge chunk
-        const uint8_t *hi = p.in + p.in_bytes;
-        for (uint32_t i = 0; i < 5; ++i) {
-            if (!((sp.edge >> i) & 1u)) continue;
-            const uint32_t c = lane + kWave * i;
-            const uint8_t *cp = sp.abase + 16 * c;
-            uint32_t byte[16];
-#pragma unroll
-            for (uint32_t b = 0; b < 16; ++b) byte[b] = (cp + b >= p.in && cp + b < hi) ? (uint32_t)cp[b] : 0u;
-            uint32_t d[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (uint32_t b = 0; b < 16; ++b) d[b >> 2] |= byte[b] << (8 * (b & 3));
-            *(u32x4a *)(stage + kStagePad + 16 * c) = u32x4a{d[0], d[1], d[2], d[3]};
-        }
+        if (c < sp.nch) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
     }
 }
 
@@ -288,9 +267,11 @@ __device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t 
     const uint64_t nblocks = (n + 3) >> 2;
     const uint8_t *gp = in + first;
     const uint32_t sh = (uint32_t)((uintptr_t)gp & 3u);
-    // every block of the wave's run is full (4 integers), and the aligned
-    // dwords around it, one dword past its end included, lie in the buffer
-    if ((first + (uint64_t)P * kWave) * 4 <= n && first >= sh && first + (uint64_t)P * kWave + 4 <= in_bytes) {
+    // every block of the wave's run is full (4 integers); the aligned dwords
+    // around a lane's bytes each hold at least one of them, so none crosses a
+    // page the stream does not touch (the one past the end is read only when
+    // the bytes are misaligned)
+    if ((first + (uint64_t)P * kWave) * 4 <= n) {
         const uint32_t *base = (const uint32_t *)(gp - sh) + (P / 4) * lane;
         const uint32_t keep = 0xFFFFFFFFu << (8u * sh);
         uint32_t codes = 0;
@@ -299,7 +280,7 @@ __device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t 
             const uint32_t x = (i == 0) ? (base[i] & keep) : base[i];
             codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
         }
-        const uint32_t e = base[P / 4] & ~keep;
+        const uint32_t e = sh ? (base[P / 4] & ~keep) : 0u;
         codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
         return 4u * P + codes;
     }
