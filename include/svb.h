@@ -30,11 +30,12 @@
  *  - Calls on different streams may run concurrently: the library keeps a
  *    separate scratch workspace per (device, stream).  Calls on one stream
  *    are ordered by the stream.
- *  - The only library-owned memory is that scratch workspace: eight ticket
- *    counters, one 8-byte status word per encoder tile of 4096 integers, and
- *    20 bytes per decoder group of 8192 integers (byte total, byte offset,
- *    value sum, value prefix); grown on demand, freed by
- *    svb_release_workspace.
+ *  - The only library-owned memory is that scratch workspace (and, for a
+ *    serving pool, the server's own buffers): 12 bytes per encoder segment of
+ *    1024 integers (byte count, byte offset), 20 bytes per decoder group of
+ *    8192 integers (byte total, byte offset, value sum, value prefix), about
+ *    96 bytes per batched segment, plus the scans' partial sums; grown on
+ *    demand, freed by svb_release_workspace.
  *  - Return value: SVB_OK (0) or a negative svb_status.  The library never
  *    aborts the process.
  */
@@ -60,13 +61,8 @@ enum svb_status {
  * control bytes describe more data than in_bytes holds. */
 #define SVB_DECODE_CORRUPT 1u
 
-/* Value the delta decoder writes to `err` if a workgroup waited about a
- * second for the running sum of the data before it (never expected: every
- * earlier piece is owned by a running workgroup; this turns a wait that
- * cannot end into an error instead of a hung device).  The output is then
- * incomplete.  The encoders report the same condition by writing
- * UINT64_MAX to out_bytes. */
-#define SVB_DECODE_STALLED 2u
+/* (Value 2 is not used: no kernel of the library waits for another
+ * workgroup, so none can stall.) */
 
 /* Value a batched decode writes to `err` when the lists hold more integers
  * than the caller's total_ints bound (nothing is decoded then). */

@@ -24,7 +24,6 @@ __all__ = [
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
-SVB_DECODE_STALLED = 2
 SVB_BATCH_OVERFLOW = 3
 
 _lib = None

@@ -11,23 +11,15 @@
 namespace svb {
 namespace {
 
-// Scratch owned by the library for one (device, stream): the per-class tile
-// ticket counters and the per-tile status words of the look-back scans.
+// Scratch owned by the library for one (device, stream): per-piece byte
+// counts, offsets and value sums of the reduce-then-scan passes.
 struct Workspace {
-    uint32_t *counters = nullptr;             // kTicketClasses * kCounterStride words
-    uint32_t base[kTicketClasses] = {};       // counter values after the last launch
-    uint64_t *flags = nullptr;                // encoder look-back: cap status words
-    uint64_t cap = 0;                         // status words
-    uint32_t epoch = 0;
-    uint8_t *scratch = nullptr;               // decoder offsets and sums
+    uint8_t *scratch = nullptr;
     uint64_t scratch_bytes = 0;
 };
 
 std::mutex g_mu;
 std::map<std::pair<int, uintptr_t>, Workspace> g_ws;
-
-constexpr uint32_t kEpochLimit = 1u << 20;  // status words carry a 20-bit epoch
-constexpr uint64_t kFlagWordsPerTile = 1;  // the encoder's byte-offset word
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SVB_OK : SVB_ERR_HIP; }
 
@@ -62,52 +54,13 @@ hipError_t timed(const char *name, hipStream_t s, F launch) {
     return e;
 }
 
-// Workspace for the calling thread's device and `s`, with room for `tiles`
-// tiles, and a fresh epoch for one launch.  Caller holds g_mu.
-int acquire_locked(hipStream_t s, uint64_t tiles, Workspace **out) {
+// Workspace of the calling thread's device and stream `s`.  Caller holds g_mu.
+int acquire_locked(hipStream_t s, Workspace **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
-    Workspace &w = g_ws[std::make_pair(dev, (uintptr_t)s)];
-    if (!w.counters) {
-        const uint64_t words = (uint64_t)kTicketClasses * kCounterStride;
-        if (hipMalloc((void **)&w.counters, words * sizeof(uint32_t)) != hipSuccess) {
-            w.counters = nullptr;
-            return SVB_ERR_NOMEM;
-        }
-        if (launch_fill(w.counters, words, 0u, s) != hipSuccess) return SVB_ERR_HIP;
-        for (uint32_t c = 0; c < kTicketClasses; ++c) w.base[c] = 0;
-    }
-    // status words of consecutive tiles sit kFlagStride words apart
-    const uint64_t words = tiles * kFlagStride;
-    if (words > w.cap) {
-        uint64_t cap = 1024;
-        while (cap < words) cap <<= 1;
-        if (w.flags) {
-            if (hipStreamSynchronize(s) != hipSuccess) return SVB_ERR_HIP;
-            (void)hipFree(w.flags);
-            w.flags = nullptr;
-            w.cap = 0;
-        }
-        if (hipMalloc((void **)&w.flags, kFlagWordsPerTile * cap * sizeof(uint64_t)) != hipSuccess) {
-            w.flags = nullptr;
-            return SVB_ERR_NOMEM;
-        }
-        if (launch_fill((uint32_t *)w.flags, 2 * kFlagWordsPerTile * cap, 0u, s) != hipSuccess) return SVB_ERR_HIP;
-        w.cap = cap;
-        w.epoch = 0;
-    }
-    w.epoch += 1;
-    if (w.epoch >= kEpochLimit) {
-        // every epoch value has been used: clear the words and start over
-        if (launch_fill((uint32_t *)w.flags, 2 * kFlagWordsPerTile * w.cap, 0u, s) != hipSuccess)
-            return SVB_ERR_HIP;
-        w.epoch = 1;
-    }
-    *out = &w;
+    *out = &g_ws[std::make_pair(dev, (uintptr_t)s)];
     return SVB_OK;
 }
-
-uint64_t *byte_flags(const Workspace &w) { return w.flags; }
 
 // At least `bytes` of decoder scratch (contents undefined).  Caller holds g_mu.
 int ensure_scratch(Workspace &w, uint64_t bytes, hipStream_t s) {
@@ -128,28 +81,6 @@ int ensure_scratch(Workspace &w, uint64_t bytes, hipStream_t s) {
     return SVB_OK;
 }
 
-// Tile queue for one launch of `grid` workgroups over `tiles` tiles.
-TileQueue make_queue(const Workspace &w, uint32_t tiles, uint32_t grid) {
-    TileQueue q;
-    q.counters = w.counters;
-    for (uint32_t c = 0; c < kTicketClasses; ++c) q.base[c] = w.base[c];
-    q.classes = grid < kTicketClasses ? grid : kTicketClasses;
-    q.num_tiles = tiles;
-    return q;
-}
-
-// After a launch: the class's tiles were taken once each, and every workgroup
-// of the class also took `past_end` tickets beyond the last tile (1 for a
-// kernel that asks for one tile at a time, 2 for the decoder, which asks two
-// tiles ahead).
-void advance_queue(Workspace &w, const TileQueue &q, uint32_t grid, uint32_t past_end) {
-    for (uint32_t c = 0; c < q.classes; ++c) {
-        const uint32_t tiles_c = (q.num_tiles - c + q.classes - 1) / q.classes;
-        const uint32_t wgs_c = (grid - c + q.classes - 1) / q.classes;
-        w.base[c] += tiles_c + past_end * wgs_c;
-    }
-}
-
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
@@ -158,32 +89,8 @@ int zero_u64(uint64_t *p, hipStream_t s) {
     return hip_status(launch_fill((uint32_t *)p, 2, 0u, s));
 }
 
-// Kernels that wait for other workgroups of the same launch (the look-back
-// kernels) are never run concurrently with each other on one device: each is
-// ordered after the previous one, whatever its stream.  Two such launches
-// sharing the device could otherwise each hold the compute units the other's
-// pending workgroups need.  Caller holds g_mu.
-std::map<int, hipEvent_t> g_lookback_done;
-
-int order_lookback_launch(hipStream_t s) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
-    auto it = g_lookback_done.find(dev);
-    if (it == g_lookback_done.end()) {
-        hipEvent_t e;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SVB_ERR_HIP;
-        g_lookback_done[dev] = e;
-        return SVB_OK;
-    }
-    return hip_status(hipStreamWaitEvent(s, it->second, 0));
-}
-
-int lookback_launched(hipStream_t s) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
-    return hip_status(hipEventRecord(g_lookback_done[dev], s));
-}
-
+// Encoding in two passes over the values: data bytes of every segment, an
+// exclusive scan of them, then each segment packed at its offset.
 int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint64_t *out_bytes,
               bool delta, void *stream) {
     hipStream_t s = (hipStream_t)stream;
@@ -191,27 +98,32 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
     if (out_bytes && !aligned8(out_bytes)) return SVB_ERR_INVALID;
     if (n == 0) return zero_u64(out_bytes, s);
     if (!in || !out || !aligned4(in)) return SVB_ERR_INVALID;
-    const uint32_t tiles = (uint32_t)((n + kTileInts - 1) / kTileInts);
-    const uint32_t grid = encode_grid(delta, tiles);
+    const uint64_t segs = (n + kSegInts - 1) / kSegInts;
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_bytes = 0, o_off = up16(4 * segs), o_scan = o_off + up16(8 * segs);
+    const uint64_t need = o_scan + up16(scan_scratch_bytes(segs));
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
-    int st = acquire_locked(s, tiles, &w);
+    int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
-    EncodeArgs a;
-    a.in = in;
-    a.n = n;
-    a.out = out;
-    a.start = start;
-    a.out_bytes = out_bytes;
-    a.q = make_queue(*w, tiles, grid);
-    a.byte_flags = byte_flags(*w);
-    a.epoch = w->epoch;
-    if ((st = order_lookback_launch(s)) != SVB_OK) return st;
-    if ((st = hip_status(timed(delta ? "encode_delta" : "encode", s, [&] { return launch_encode(a, delta, grid, s); }))) !=
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    EncodeStream e;
+    e.in = in;
+    e.n = n;
+    e.out = out;
+    e.start = start;
+    uint32_t *seg_bytes = (uint32_t *)(sc + o_bytes);
+    uint64_t *seg_off = (uint64_t *)(sc + o_off);
+    if ((st = hip_status(timed("encode_sizes", s, [&] { return launch_encode_sizes(e, delta, seg_bytes, segs, s); }))) !=
         SVB_OK)
         return st;
-    advance_queue(*w, a.q, grid, kEncodeTicketsPastEnd);
-    return lookback_launched(s);
+    if ((st = hip_status(timed("scan_offsets", s, [&] {
+             return launch_scan(seg_bytes, seg_off, segs, true, 0u, s, nullptr, sc + o_scan);
+         }))) != SVB_OK)
+        return st;
+    return hip_status(timed(delta ? "encode_delta" : "encode", s,
+                            [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s); }));
 }
 
 int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
@@ -234,7 +146,7 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *w;
-    int st = acquire_locked(s, 1, &w);
+    int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
     if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
     uint8_t *sc = w->scratch;
@@ -335,7 +247,7 @@ int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
     const uint64_t scan_bytes = std::max(scan_scratch_bytes(M), scan_scratch_bytes(T));
     const uint64_t need = o_scan + up16(scan_bytes);
     Workspace *w;
-    int st = acquire_locked(s, 1, &w);
+    int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
     if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
     uint8_t *sc = w->scratch;
@@ -435,32 +347,6 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
 
 }  // namespace
 
-uint32_t persistent_grid(const void *kernel, uint32_t num_tiles, uint32_t block_threads) {
-    static std::mutex mu;
-    static std::map<std::pair<int, const void *>, uint32_t> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    uint32_t grid = 0;
-    {
-        std::lock_guard<std::mutex> lock(mu);
-        auto it = cache.find(std::make_pair(dev, kernel));
-        if (it != cache.end()) {
-            grid = it->second;
-        } else {
-            int cus = 0, per_cu = 0;
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-                cus = 256;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block_threads, 0) != hipSuccess ||
-                per_cu <= 0)
-                per_cu = 4;
-            grid = (uint32_t)(cus * per_cu);
-            cache[std::make_pair(dev, kernel)] = grid;
-        }
-    }
-    if (grid > num_tiles) grid = num_tiles;
-    return grid ? grid : 1u;
-}
-
 // Batched decode for the serving runtime (same path as svb_decode_batch).
 int serve_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
                        const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
@@ -552,16 +438,9 @@ void svb_release_workspace(void) {
     for (auto &kv : g_ws) {
         (void)hipSetDevice(kv.first.first);
         (void)hipDeviceSynchronize();
-        if (kv.second.counters) (void)hipFree(kv.second.counters);
-        if (kv.second.flags) (void)hipFree(kv.second.flags);
         if (kv.second.scratch) (void)hipFree(kv.second.scratch);
     }
     g_ws.clear();
-    for (auto &kv : g_lookback_done) {
-        (void)hipSetDevice(kv.first);
-        (void)hipEventDestroy(kv.second);
-    }
-    g_lookback_done.clear();
     (void)hipSetDevice(cur);
 }
 

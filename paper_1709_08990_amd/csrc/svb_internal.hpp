@@ -8,40 +8,8 @@
 
 namespace svb {
 
-// Blocks (control bytes) per thread per tile: a tile is 256 * K blocks = 1024 K integers.
-constexpr int kWorkgroupThreads = 256;
-#ifndef SVB_BLOCKS_PER_THREAD
-#define SVB_BLOCKS_PER_THREAD 4
-#endif
-constexpr int kBlocksPerThread = SVB_BLOCKS_PER_THREAD;
-constexpr uint64_t kTileInts = 256ull * kBlocksPerThread * 4ull;
-
-// Words between consecutive tiles' status words (1 = packed).
-#ifndef SVB_FLAG_STRIDE
-#define SVB_FLAG_STRIDE 1
-#endif
-constexpr uint64_t kFlagStride = SVB_FLAG_STRIDE;
-
-// Tiles are handed out by kTicketClasses ticket counters.  Workgroup b belongs
-// to class b % classes (the dispatcher places workgroups on the eight XCDs
-// round-robin, so a class is an XCD) and takes tiles t with t % classes equal
-// to its class, in increasing order.  One shared counter would serialise every
-// ticket on a single address; eight spread the atomics over eight lines.
-constexpr uint32_t kTicketClasses = 8;
-constexpr uint32_t kCounterStride = 32;  // uint32 words between counters (128 bytes)
-
-// Tickets each workgroup takes beyond the last tile of its class, per kernel.
-constexpr uint32_t kEncodeTicketsPastEnd = 1;
-
-struct TileQueue {
-    uint32_t *counters;             // kTicketClasses counters, kCounterStride words apart
-    uint32_t base[kTicketClasses];  // value of each counter when the launch starts
-    uint32_t classes;               // min(kTicketClasses, grid)
-    uint32_t num_tiles;
-};
-
-// Decoding geometry.  A segment is what one wave decodes at a time: 64 lanes x
-// 16 integers, each lane owning four consecutive control bytes.  A group is
+// Geometry.  A segment is what one wave decodes or encodes at a time: 64 lanes
+// x 16 integers, lane l owning control bytes l, l + 64, l + 128, l + 192.  A group is
 // kGroupSegs consecutive segments, walked in order by one wave; the pre-pass
 // and the scans work per group.
 constexpr uint32_t kSegInts = 1024;
@@ -73,17 +41,6 @@ struct DecodeArgs {
     const uint64_t *goff;  // data-stream byte offset of each group
     uint32_t *gvsum;       // value sum of each group (written in value-sum mode)
     const uint32_t *gvpre; // start + exclusive value prefix of each group (read in delta mode)
-};
-
-struct EncodeArgs {
-    const uint32_t *in;
-    uint64_t n;
-    uint8_t *out;
-    uint32_t start;
-    uint64_t *out_bytes;
-    TileQueue q;
-    uint64_t *byte_flags;
-    uint32_t epoch;
 };
 
 // Decoding: mode 0 plain, 1 delta (running sum), 2 value sums per group.
@@ -152,15 +109,19 @@ enum BatchPhase {
 };
 hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s);
 
-// Encoding (persistent, decoupled look-back over tile byte totals).
-uint32_t encode_grid(bool delta, uint32_t num_tiles);
-hipError_t launch_encode(const EncodeArgs &a, bool delta, uint32_t grid, hipStream_t s);
+// Encoding (two passes: data bytes per segment, scan, pack).
+// A stream to encode: n values at `in`; the stream (control bytes first) is
+// written at `out`.  Delta encoding starts from `start`.
+struct EncodeStream {
+    const uint32_t *in;
+    uint64_t n;
+    uint8_t *out;
+    uint32_t start;
+};
+hipError_t launch_encode_sizes(const EncodeStream &e, bool delta, uint32_t *seg_bytes, uint64_t segs, hipStream_t s);
+hipError_t launch_encode_pack(const EncodeStream &e, bool delta, const uint64_t *seg_off, uint64_t segs,
+                              uint64_t *out_bytes, hipStream_t s);
 hipError_t launch_copy(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t s);
 hipError_t launch_fill(uint32_t *out, uint64_t n, uint32_t value, hipStream_t s);
-
-// Workgroups for a persistent launch of `kernel` over `num_tiles` tiles:
-// resident workgroups per CU (from the occupancy calculator) times the CU count,
-// capped by the number of tiles.
-uint32_t persistent_grid(const void *kernel, uint32_t num_tiles, uint32_t block_threads);
 
 }  // namespace svb

@@ -301,15 +301,6 @@ __device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t 
 // --------------------------------------------------------------------------
 // encoding one segment
 
-// A stream to encode: n values at `in`; the stream (control bytes first) is
-// written at `out`.  Delta encoding starts from `start`.
-struct EncodeStream {
-    const uint32_t *in;
-    uint64_t n;
-    uint8_t *out;
-    uint32_t start;
-};
-
 constexpr uint32_t kEncStageBytes = 4160;  // 16 x 257 bytes of span + padding
 
 // The lane's four blocks of segment s: the values (or differences, Section 2)
