@@ -215,6 +215,10 @@ struct BatchCall {
 };
 
 // chunk = 0: the tuned choice for this kind of call.
+#ifndef SVB_SUMS_CHUNK
+#define SVB_SUMS_CHUNK 0
+#endif
+
 int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (c.m == 0) return SVB_OK;
@@ -292,7 +296,10 @@ int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
         return st;
     if ((st = run("batch_desc", kBatchDesc)) != SVB_OK) return st;
     if (!c.encode && delta) {
-        if ((st = run("batch_task_sums", kBatchItemSums)) != SVB_OK) return st;
+        a.chunk = SVB_SUMS_CHUNK ? SVB_SUMS_CHUNK : C;
+        st = run("batch_task_sums", kBatchItemSums);
+        a.chunk = C;
+        if (st != SVB_OK) return st;
         if ((st = hip_status(timed("batch_scan_sums", s, [&] {
                  return launch_scan(a.ivsum, a.ivpre, T, false, 0u, s, nullptr, scan_scr);
              }))) != SVB_OK)

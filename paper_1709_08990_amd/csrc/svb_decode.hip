@@ -24,8 +24,8 @@
 // segment's data bytes are copied into LDS with coalesced 16-byte loads, and
 // each integer is cut out of the aligned 8 bytes around the 4 bytes that end
 // at its last byte with two byte-align instructions: the byte shuffle of
-// Fig. 4 without a shuffle table.  A wave loads segment s + 1 while it
-// decodes segment s.
+// Fig. 4 without a shuffle table.  A wave loads the next segment (the next
+// two, for plain decoding) while it decodes segment s.
 #include "svb_device.hpp"
 #include "svb_internal.hpp"
 #include "svb_segment.hpp"
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
     const uint64_t s0 = g * kGroupSegs;
     const uint64_t s_end = s0 + kGroupSegs < segs ? s0 + kGroupSegs : segs;
     uint32_t carry = (MODE == kDelta) ? p.gvpre[g] : 0u;
-    Walker w;
+    Walker<MODE == kPlain ? 2 : 1> w;  // plain decoding waits on memory: two segments in flight
     walker_begin(p, w, s0, s_end, p.goff[g], lane);
     for (uint64_t s = s0; s < s_end; ++s) {
         SegPlan seg;

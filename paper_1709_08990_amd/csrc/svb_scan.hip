@@ -7,9 +7,10 @@
 // (delta carries).  An optional `total` receives the sum of all m values
 // (64-bit, or 32-bit plus start modulo 2^32).
 //
-// Up to kSingleMax values: one workgroup of 1024 threads walks the array in
-// steps of 16384.  Above that: reduce-then-scan over tiles of 16384 values
-// (tile sums, one-workgroup scan of the tile sums, per-tile scan with carry).
+// Up to kSingleMax (16384) values: one workgroup of 1024 threads.  Above
+// that: reduce-then-scan over tiles of 16384 values (tile sums, one-workgroup
+// scan of the tile sums, per-tile scan with carry); one workgroup walking a
+// longer array step by step was measured slower than the three launches.
 #include <type_traits>
 
 #include "svb_device.hpp"
@@ -23,7 +24,7 @@ constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanPer = 16;
 constexpr uint32_t kScanTile = kScanThreads * kScanPer;  // values per workgroup step
 constexpr uint32_t kScanWaves = kScanThreads / kWave;
-constexpr uint64_t kSingleMax = 4ull * kScanTile;
+constexpr uint64_t kSingleMax = kScanTile;
 
 template <bool WIDE>
 using acc_t = typename std::conditional<WIDE, uint64_t, uint32_t>::type;

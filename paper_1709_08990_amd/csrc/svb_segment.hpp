@@ -113,61 +113,78 @@ __device__ __forceinline__ void span_to_lds(const DecodeArgs &, const Span &sp, 
     }
 }
 
-// Walks consecutive segments [s, s_end) of one wave with a one-segment
-// software pipeline: each step stages segment s into LDS and, before
-// returning, requests segment s + 1's data and segment s + 2's control bytes,
-// so that they are in flight while s is decoded and stored.
+// Walks consecutive segments [s, s_end) of one wave with a software pipeline
+// D segments deep (1 or 2): when segment s is staged into LDS, the data of
+// segments s + 1 .. s + D and the control bytes of s + D + 1 have been
+// requested, so they are in flight while s is decoded and stored.  Depth 2
+// keeps twice the bytes in flight per wave at the cost of occupancy: it pays
+// where the walk waits on memory (plain decoding), not where extraction work
+// dominates (the delta passes).
+struct WalkSlot {
+    SegPlan plan;
+    uint32_t sh16;  // (data + boff) mod 16
+    uint64_t boff;  // byte offset of the segment in the data stream
+    Span sp;
+};
+
+template <uint32_t D>
 struct Walker {
+    static_assert(D == 1 || D == 2, "walker depth 1 or 2");
     const uint8_t *data;    // start of the data stream
     uint64_t data_bytes;    // bytes of the buffer from `data` on
     uint64_t s, s_end;
-    uint64_t boff;          // byte offset of segment s in the data stream
-    SegPlan cur;            // plan of segment s
-    uint32_t sh16;          // (data + boff) mod 16
-    Span sp;                // segment s's data in flight
-    SegCtrl ahead;          // control bytes of segment s + 1
+    WalkSlot q[D];          // q[0]: segment s, q[D - 1]: segment s + D - 1
+    SegCtrl ahead;          // control bytes of segment s + D
     bool corrupt;
 };
 
-__device__ __forceinline__ void walker_begin(const DecodeArgs &p, Walker &w, uint64_t s0, uint64_t s_end,
+// Plans segment t from its control bytes and requests its data.
+__device__ __forceinline__ void walker_issue(const DecodeArgs &p, const uint8_t *data, uint64_t t, const SegCtrl &c,
+                                             uint64_t boff, uint32_t lane, WalkSlot &q) {
+    q.plan = plan_segment(p, t, c, lane);
+    q.boff = boff;
+    const uint8_t *at = data + boff;
+    q.sh16 = (uint32_t)((uintptr_t)at & 15u);
+    q.sp.abase = at - q.sh16;
+    q.sp.nch = (q.sh16 + q.plan.total + 15) >> 4;
+    span_load(p, q.sp, lane);
+}
+
+template <uint32_t D>
+__device__ __forceinline__ void walker_begin(const DecodeArgs &p, Walker<D> &w, uint64_t s0, uint64_t s_end,
                                              uint64_t boff, uint32_t lane) {
     const uint64_t nblocks = (p.n + 3) >> 2;
     w.data = p.in + nblocks;
     w.data_bytes = p.in_bytes - nblocks;
     w.s = s0;
     w.s_end = s_end;
-    w.boff = boff;
     w.corrupt = false;
-    w.cur = plan_segment(p, s0, load_seg_ctrl(p, s0, lane), lane);
-    w.sh16 = (uint32_t)((uintptr_t)(w.data + boff) & 15u);
-    w.sp.abase = w.data + boff - w.sh16;
-    w.sp.nch = (w.sh16 + w.cur.total + 15) >> 4;
-    span_load(p, w.sp, lane);
+    walker_issue(p, w.data, s0, load_seg_ctrl(p, s0, lane), boff, lane, w.q[0]);
+    if (D == 2 && s0 + 1 < s_end)
+        walker_issue(p, w.data, s0 + 1, load_seg_ctrl(p, s0 + 1, lane), boff + w.q[0].plan.total, lane, w.q[D - 1]);
     w.ahead = SegCtrl{{0u, 0u, 0u, 0u}};
-    if (s0 + 1 < s_end) w.ahead = load_seg_ctrl(p, s0 + 1, lane);
+    if (s0 + D < s_end) w.ahead = load_seg_ctrl(p, s0 + D, lane);
 }
 
 // Stages segment w.s into `stage`, returns its plan and data alignment, and
-// advances the walker to w.s + 1 (requesting its data).
-__device__ __forceinline__ void walker_step(const DecodeArgs &p, Walker &w, uint8_t *stage, uint32_t lane,
+// advances the walker to w.s + 1 (requesting the data of w.s + D).
+template <uint32_t D>
+__device__ __forceinline__ void walker_step(const DecodeArgs &p, Walker<D> &w, uint8_t *stage, uint32_t lane,
                                             SegPlan &seg, uint32_t &seg_sh16) {
-    if (w.boff + w.cur.total > w.data_bytes) w.corrupt = true;
-    span_to_lds(p, w.sp, stage, lane);
+    if (w.q[0].boff + w.q[0].plan.total > w.data_bytes) w.corrupt = true;
+    span_to_lds(p, w.q[0].sp, stage, lane);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    seg = w.cur;
-    seg_sh16 = w.sh16;
-    w.boff += seg.total;
+    seg = w.q[0].plan;
+    seg_sh16 = w.q[0].sh16;
+    const uint64_t next_boff = w.q[D - 1].boff + w.q[D - 1].plan.total;
+    if (D == 2) w.q[0] = w.q[D - 1];
     ++w.s;
-    if (w.s < w.s_end) {
-        w.cur = plan_segment(p, w.s, w.ahead, lane);
-        const uint8_t *q = w.data + w.boff;
-        w.sh16 = (uint32_t)((uintptr_t)q & 15u);
-        w.sp.abase = q - w.sh16;
-        w.sp.nch = (w.sh16 + w.cur.total + 15) >> 4;
-        span_load(p, w.sp, lane);
-        if (w.s + 1 < w.s_end) w.ahead = load_seg_ctrl(p, w.s + 1, lane);
+    const uint64_t t = w.s + D - 1;  // the segment whose data is requested now
+    if (t < w.s_end) {
+        walker_issue(p, w.data, t, w.ahead, next_boff, lane, w.q[D - 1]);
+        if (t + 1 < w.s_end) w.ahead = load_seg_ctrl(p, t + 1, lane);
     }
 }
 

@@ -135,7 +135,7 @@ def test_batch_edge_sizes(chunk, delta):
 
 @pytest.mark.parametrize("delta", [False, True])
 def test_batch_many_small_lists(delta):
-    """More than 65536 lists and tasks, so the scans take the multi-workgroup path."""
+    """70,000 lists (more than 16384 lists and tasks), so the scans take the multi-workgroup path."""
     rng = np.random.default_rng(21)
     sizes = rng.integers(0, 48, size=70_000)
     sizes[::9_973] = rng.integers(9_000, 30_000, size=sizes[::9_973].size)
