@@ -161,6 +161,36 @@ def summarize_counters(fetch_csv, write_csv, out_md, command):
     print("\n".join(lines))
 
 
+def summarize_trace(stats_csv, out_md, title, command, bench_json=None):
+    """Turns a rocprofv3 --kernel-trace --stats kernel_stats.csv into a short table, and, given
+    the bench line of the same command, puts the dominant kernel's HIP-event average beside
+    rocprofv3's."""
+    rows = []
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                         float(r["MinNs"]), float(r["MaxNs"])))
+    rows.sort(key=lambda r: -r[2])
+    lines = ["# %s" % title, "", "rocprofv3 kernel-trace summary (kernel_stats.csv) of:", "", "    " + command, "",
+             "| kernel | calls | total us | average us | min us | max us |", "|---|---|---|---|---|---|"]
+    for name, calls, tot, avg, mn, mx in rows:
+        short = name if len(name) <= 90 else name[:87] + "..."
+        lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %.1f |" % (short, calls, tot / 1e3, avg / 1e3, mn / 1e3,
+                                                                  mx / 1e3))
+    if bench_json:
+        with open(bench_json) as fh:
+            line = json.loads(fh.read().strip().splitlines()[-1])
+        rf = line["roofline"]
+        dom = [r for r in rows if DOMINANT_SYMBOL in r[0]]
+        lines += ["", "bench.py, same command: dominant kernel `%s` %.1f us per launch by the library's HIP events;"
+                  % (rf["kernel"], 1e3 * rf["kernel_ms"]),
+                  "rocprofv3 average for `%s`: %s us." % (DOMINANT_SYMBOL, "%.1f" % (dom[0][3] / 1e3) if dom else "n/a")]
+    lines += ["", "source_digest: %s" % source_digest(), ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 # ------------------------------------------------------------------ GPU measurement
 
 def event_loop(fn, steps, torch, before=None):
@@ -283,7 +313,7 @@ def measure_copy(svb, torch, steps):
             "frac_of_peak": gbs(8 * COPY_WORDS, ms) / HBM_PEAK_GBS, "ok": ok}
 
 
-def measure_batched(svb, torch, np, inputs, steps, warmup):
+def measure_batched(svb, torch, np, inputs, steps, warmup, per_list=True):
     """C4: 200,000 posting lists (rank-size Zipf lengths in [1, 2^20], about 3e8 integers, sorted sets
     over [0, 2^31)), delta-coded from 0.  Batched encode, autotuned batched delta decode, and one
     svb_delta_decode call per list on the same streams."""
@@ -319,6 +349,9 @@ def measure_batched(svb, torch, np, inputs, steps, warmup):
            "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
            "kernels_ms": kms, "round_trip_ok": ok,
            "encode": {"ms_per_call": 1e3 * ewall / steps, "uint32_per_s": total / ewall * steps, "kernels_ms": ekms}}
+    if not per_list:
+        del x_dev, comp, out
+        return res
     # one svb_delta_decode call per list, same streams, same output
     L = svb.lib()
     h_sizes = sizes.cpu().numpy().astype(np.uint64)
@@ -483,12 +516,24 @@ def main():
     ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 200,000-list batched measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-per-list", action="store_true",
+                    help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of each open-loop serving window (seconds of arrivals)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
-    ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} -- python3 bench.py "
-                    "--steps 5 --warmup 2 --no-cpu-baseline --no-2p28 --no-batched --no-serving")
+    ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
+                    "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
+                    "--no-2p28 --no-batched --no-serving")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
+    ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
+                    "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
+                    "--no-2p28 --no-batched --no-serving")
+    ap.add_argument("--trace-bench-json", default=None,
+                    help="bench line printed by the traced command (for --summarize-trace)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, command=args.trace_command, bench_json=args.trace_bench_json)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, command=args.counter_command)
         return
@@ -570,14 +615,16 @@ def main():
     del flush
     if not args.no_batched:
         log("batched: generating 200,000 posting lists")
-        rb = measure_batched(svb, torch, np, inputs, max(5, args.steps // 2), 2)
-        assert rb["round_trip_ok"] and rb["one_call_per_list"]["round_trip_ok"], "batched decode mismatch"
+        rb = measure_batched(svb, torch, np, inputs, max(5, args.steps // 2), 2, per_list=not args.no_per_list)
+        assert rb["round_trip_ok"], "batched decode mismatch"
         single = line.get("at_2p28", {}).get("delta_docids", {}).get("uint32_per_s", line["value"])
         rb["vs_single_array"] = rb["uint32_per_s"] / single
-        rb["vs_one_call_per_list"] = rb["uint32_per_s"] / rb["one_call_per_list"]["uint32_per_s"]
+        if "one_call_per_list" in rb:
+            assert rb["one_call_per_list"]["round_trip_ok"], "per-list decode mismatch"
+            rb["vs_one_call_per_list"] = rb["uint32_per_s"] / rb["one_call_per_list"]["uint32_per_s"]
         line["batched"] = rb
-        log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array, %.1fx one call per list)"
-            % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"], rb["vs_one_call_per_list"]))
+        log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array)"
+            % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)
