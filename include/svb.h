@@ -200,10 +200,13 @@ int svb_set_batch_chunk(int kind, uint32_t chunk);
  * batching over the batched decoder (the paper's setting of Section 5: a
  * search engine decoding the posting lists a query asks for).
  *
- * svb_server_create copies the pool table to the host once: m lists whose
- * streams lie in `in` at in_off[i] (in_bytes[i] bytes, counts[i] integers),
- * delta-coded from starts[i] if `starts` is not NULL (all device arrays; they
- * and `in` must stay valid while the server lives).  The server owns an output
+ * svb_server_create takes a pool of m lists whose streams lie in `in` at
+ * in_off[i] (in_bytes[i] bytes, counts[i] integers), delta-coded from
+ * starts[i] if `starts` is not NULL (all device arrays; `in` must stay valid
+ * while the server lives).  It copies the counts to the host and builds the
+ * pool's task index on the device once (64 bytes per segment of 1024
+ * integers: each segment's byte offset and running-sum carry), refusing a
+ * pool with a corrupt list with SVB_ERR_INVALID.  The server owns an output
  * arena of arena_bytes, `streams` stream slots (1..16; a slot runs one batch
  * at a time) and launches at most max_batch_lists lists per batch.
  *
@@ -224,7 +227,8 @@ int svb_set_batch_chunk(int kind, uint32_t chunk);
  * address.  svb_server_stats writes up to `cap` counters: batches, lists,
  * integers, queries admitted, queries completed, most slots busy at once, the
  * decoders' err flags (OR), arena peak (integers), queries waiting, admitted
- * but not launched, arena integers in use.  svb_server_destroy waits for the
+ * but not launched, arena integers in use, scheduling steps, steps whose host
+ * work took over 1 ms, the longest step (microseconds).  svb_server_destroy waits for the
  * device and frees everything.  One server may be driven from one thread at a
  * time (calls are serialised by a lock).
  */
@@ -243,18 +247,20 @@ int svb_server_destroy(void *server);
  * svb_server_replay drives the server from the calling thread with a query
  * trace and measures latency (a load generator for the serving loop).  Query i
  * asks for lists[qoff[i] .. qoff[i+1]) (host arrays; every query names at
- * least one list) and gets the id id_base + i.  Open loop (arrival_s != NULL):
- * query i is submitted once arrival_s[i] seconds have passed since the call
- * began; its latency runs from arrival_s[i] to the moment the host sees its
- * batch complete.  Closed loop (arrival_s == NULL): `outstanding` queries are
- * kept in the system, latency runs from submission.  Results are released as
- * soon as they complete (nothing is read back).  latency_s[i] receives
+ * least one list).  Open loop (arrival_s != NULL): query i is submitted once
+ * arrival_s[i] seconds have passed since the call began; its latency runs
+ * from arrival_s[i] to the moment the host sees its batch complete.  Closed
+ * loop (arrival_s == NULL): `outstanding` queries are kept in the system,
+ * latency runs from submission.  Replayed queries share the arena and the
+ * batches with queries of svb_server_submit but are never polled: their
+ * results are released as soon as they complete.  latency_s[i] receives
  * seconds; *wall_s (if not NULL) the call's duration.  Returns SVB_OK, or a
- * negative status (bad trace, an id already live, a query that can never be
- * admitted, a HIP error) with the server's state as of the failure.
+ * negative status (bad trace, a query that can never be admitted, an arena
+ * held by unreleased results, a HIP error) with the server's state as of the
+ * failure.
  */
 int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
-                      uint32_t outstanding, uint64_t id_base, double *latency_s, double *wall_s);
+                      uint32_t outstanding, double *latency_s, double *wall_s);
 
 /* Message for a status code (static string). */
 const char *svb_strerror(int status);

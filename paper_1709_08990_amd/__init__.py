@@ -64,7 +64,7 @@ def lib():
             "svb_server_arena": (vp, [vp]),
             "svb_server_stats": (i32, [vp, vp, u32]),
             "svb_server_destroy": (i32, [vp]),
-            "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, u64, vp, vp]),
+            "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, vp, vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -266,7 +266,8 @@ def svb_server_arena(server):
 
 
 SERVER_STATS = ("batches", "lists", "integers", "admitted", "completed", "peak_busy_slots", "err",
-                "arena_peak_ints", "waiting", "admitted_not_launched", "arena_in_use_ints")
+                "arena_peak_ints", "waiting", "admitted_not_launched", "arena_in_use_ints", "steps", "slow_steps",
+                "max_step_us")
 
 
 def svb_server_stats(server):
@@ -280,7 +281,7 @@ def svb_server_destroy(server):
     return _check(lib().svb_server_destroy(server), "svb_server_destroy")
 
 
-def svb_server_replay(server, picks, arrivals=None, outstanding=0, id_base=0):
+def svb_server_replay(server, picks, arrivals=None, outstanding=0):
     """Replays queries open loop at ``arrivals`` (seconds) or, with arrivals None, closed loop with
     ``outstanding`` queries in flight.  picks: a sequence of list-id arrays, or a pair (qoff, ids)
     with query i asking for ids[qoff[i]:qoff[i+1]].  Returns (latencies in seconds, wall seconds)."""
@@ -302,7 +303,7 @@ def svb_server_replay(server, picks, arrivals=None, outstanding=0, id_base=0):
     lat = np.zeros(max(1, nq), dtype=np.float64)
     wall = ctypes.c_double(0.0)
     _check(lib().svb_server_replay(server, nq, qoff.ctypes.data, ids.ctypes.data,
-                                   None if arr is None else arr.ctypes.data, int(outstanding), int(id_base),
+                                   None if arr is None else arr.ctypes.data, int(outstanding),
                                    lat.ctypes.data, ctypes.addressof(wall)), "svb_server_replay")
     return lat[:nq], wall.value
 

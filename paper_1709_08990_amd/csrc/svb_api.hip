@@ -214,48 +214,53 @@ struct BatchCall {
     uint32_t *err;
 };
 
-// chunk = 0: the tuned choice for this kind of call.
-#ifndef SVB_SUMS_CHUNK
-#define SVB_SUMS_CHUNK 0
-#endif
+// Scratch layout of a batched call over at most T tasks and M lists.
+struct BatchLayout {
+    uint64_t o_litems, o_lbase, o_ilist, o_ifirst, o_ibytes, o_ioff, o_ivsum, o_ivpre, o_desc, o_scan, need;
+};
 
-int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
-    hipStream_t s = (hipStream_t)stream;
-    if (c.m == 0) return SVB_OK;
+BatchLayout batch_layout(uint64_t M, uint64_t T) {
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    BatchLayout L;
+    L.o_litems = 0;
+    L.o_lbase = L.o_litems + up16(4 * M);
+    L.o_ilist = L.o_lbase + up16(4 * (M + 1));
+    L.o_ifirst = L.o_ilist + up16(4 * T);
+    L.o_ibytes = L.o_ifirst + up16(4 * T);
+    L.o_ioff = L.o_ibytes + up16(4 * T);
+    L.o_ivsum = L.o_ioff + up16(8 * T);
+    L.o_ivpre = L.o_ivsum + up16(4 * T);
+    L.o_desc = (L.o_ivpre + up16(4 * T) + 63) & ~63ull;
+    L.o_scan = L.o_desc + 64 * T;
+    L.need = L.o_scan + up16(std::max(scan_scratch_bytes(M), scan_scratch_bytes(T)));
+    return L;
+}
+
+// Argument checks shared by the batched calls; t_cap receives the task bound.
+// Only a task index (no_out) comes without an output.
+int check_batch(const BatchCall &c, bool no_out, uint64_t *t_cap) {
     if (c.m >= (1u << 31)) return SVB_ERR_INVALID;
-    if (!c.counts || !c.in_off || !c.in || !c.out_off || !c.out) return SVB_ERR_INVALID;
+    if (!c.counts || !c.in_off || !c.in) return SVB_ERR_INVALID;
+    if (no_out ? (c.out || c.out_off || c.encode) : (!c.out || !c.out_off)) return SVB_ERR_INVALID;
     if (!c.encode && !c.in_bytes) return SVB_ERR_INVALID;
-    if (!aligned8(c.counts) || !aligned8(c.in_off) || !aligned8(c.out_off)) return SVB_ERR_INVALID;
+    if (!aligned8(c.counts) || !aligned8(c.in_off) || (c.out_off && !aligned8(c.out_off))) return SVB_ERR_INVALID;
     if ((c.in_bytes && !aligned8(c.in_bytes)) || (c.out_bytes && !aligned8(c.out_bytes))) return SVB_ERR_INVALID;
     if ((c.starts && !aligned4(c.starts)) || (c.err && !aligned4(c.err))) return SVB_ERR_INVALID;
-    if (c.encode ? !aligned4(c.in) : !aligned4(c.out)) return SVB_ERR_INVALID;
+    if (c.encode ? !aligned4(c.in) : (c.out && !aligned4(c.out))) return SVB_ERR_INVALID;
+    const uint64_t t = (uint64_t)c.m + (c.total_ints + kSegInts - 1) / kSegInts;
+    if (c.total_ints > (1ull << 50) || t >= (1ull << 31)) return SVB_ERR_INVALID;
+    *t_cap = t;
+    return SVB_OK;
+}
+
+// Builds the task table of a batched call in scratch `sc` (laid out by
+// batch_layout): tasks, byte offsets, descriptors, and for delta decoding the
+// carries.  Leaves `a` ready for the walk.
+int prepare_batch(const BatchCall &c, uint32_t C, uint64_t T, uint8_t *sc, BatchArgs &a, hipStream_t s) {
     const bool delta = c.starts != nullptr;
-    const int kind = 2 * (c.encode ? 1 : 0) + (delta ? 1 : 0);
-    std::lock_guard<std::mutex> lock(g_mu);
-    const uint32_t C = chunk ? chunk : tuned_chunk(kind);
-    if (!valid_chunk(C)) return SVB_ERR_INVALID;
-    const uint64_t t_cap64 = (uint64_t)c.m + (c.total_ints + kSegInts - 1) / kSegInts;
-    if (c.total_ints > (1ull << 50) || t_cap64 >= (1ull << 31)) return SVB_ERR_INVALID;
-    const uint64_t T = t_cap64, M = c.m;
-    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
-    const uint64_t o_litems = 0;
-    const uint64_t o_lbase = o_litems + up16(4 * M);
-    const uint64_t o_ilist = o_lbase + up16(4 * (M + 1));
-    const uint64_t o_ifirst = o_ilist + up16(4 * T);
-    const uint64_t o_ibytes = o_ifirst + up16(4 * T);
-    const uint64_t o_ioff = o_ibytes + up16(4 * T);
-    const uint64_t o_ivsum = o_ioff + up16(8 * T);
-    const uint64_t o_ivpre = o_ivsum + up16(4 * T);
-    const uint64_t o_desc = (o_ivpre + up16(4 * T) + 63) & ~63ull;
-    const uint64_t o_scan = o_desc + 64 * T;
-    const uint64_t scan_bytes = std::max(scan_scratch_bytes(M), scan_scratch_bytes(T));
-    const uint64_t need = o_scan + up16(scan_bytes);
-    Workspace *w;
-    int st = acquire_locked(s, &w);
-    if (st != SVB_OK) return st;
-    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
-    uint8_t *sc = w->scratch;
-    BatchArgs a = {};
+    const uint64_t M = c.m;
+    const BatchLayout L = batch_layout(M, T);
+    a = BatchArgs{};
     a.m = c.m;
     a.counts = c.counts;
     a.in_off = c.in_off;
@@ -268,18 +273,19 @@ int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
     a.out_bytes = c.encode ? c.out_bytes : nullptr;
     a.starts = c.starts;
     a.err = c.encode ? nullptr : c.err;
-    a.litems = (uint32_t *)(sc + o_litems);
-    a.lbase = (uint32_t *)(sc + o_lbase);
-    a.item_list = (uint32_t *)(sc + o_ilist);
-    a.item_first = (uint32_t *)(sc + o_ifirst);
+    a.litems = (uint32_t *)(sc + L.o_litems);
+    a.lbase = (uint32_t *)(sc + L.o_lbase);
+    a.item_list = (uint32_t *)(sc + L.o_ilist);
+    a.item_first = (uint32_t *)(sc + L.o_ifirst);
     a.t_cap = (uint32_t)T;
     a.chunk = C;
-    a.ibytes = (uint32_t *)(sc + o_ibytes);
-    a.ioff = (uint64_t *)(sc + o_ioff);
-    a.ivsum = (uint32_t *)(sc + o_ivsum);
-    a.ivpre = (uint32_t *)(sc + o_ivpre);
-    a.desc = (TaskDesc *)(sc + o_desc);
-    void *scan_scr = sc + o_scan;
+    a.ibytes = (uint32_t *)(sc + L.o_ibytes);
+    a.ioff = (uint64_t *)(sc + L.o_ioff);
+    a.ivsum = (uint32_t *)(sc + L.o_ivsum);
+    a.ivpre = (uint32_t *)(sc + L.o_ivpre);
+    a.desc = (TaskDesc *)(sc + L.o_desc);
+    void *scan_scr = sc + L.o_scan;
+    int st;
     auto run = [&](const char *name, int phase) {
         return hip_status(timed(name, s, [&] { return launch_batch(a, phase, c.encode, delta, s); }));
     };
@@ -296,17 +302,35 @@ int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
         return st;
     if ((st = run("batch_desc", kBatchDesc)) != SVB_OK) return st;
     if (!c.encode && delta) {
-        a.chunk = SVB_SUMS_CHUNK ? SVB_SUMS_CHUNK : C;
-        st = run("batch_task_sums", kBatchItemSums);
-        a.chunk = C;
-        if (st != SVB_OK) return st;
+        if ((st = run("batch_task_sums", kBatchItemSums)) != SVB_OK) return st;
         if ((st = hip_status(timed("batch_scan_sums", s, [&] {
                  return launch_scan(a.ivsum, a.ivpre, T, false, 0u, s, nullptr, scan_scr);
              }))) != SVB_OK)
             return st;
         if ((st = run("batch_carries", kBatchCarries)) != SVB_OK) return st;
     }
-    return run(c.encode ? "batch_encode" : "batch_decode", kBatchWork);
+    return SVB_OK;
+}
+
+// chunk = 0: the tuned choice for this kind of call.
+int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (c.m == 0) return SVB_OK;
+    uint64_t T = 0;
+    int st = check_batch(c, false, &T);
+    if (st != SVB_OK) return st;
+    const bool delta = c.starts != nullptr;
+    const int kind = 2 * (c.encode ? 1 : 0) + (delta ? 1 : 0);
+    std::lock_guard<std::mutex> lock(g_mu);
+    const uint32_t C = chunk ? chunk : tuned_chunk(kind);
+    if (!valid_chunk(C)) return SVB_ERR_INVALID;
+    Workspace *w;
+    if ((st = acquire_locked(s, &w)) != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, batch_layout(c.m, T).need, s)) != SVB_OK) return st;
+    BatchArgs a;
+    if ((st = prepare_batch(c, C, T, w->scratch, a, s)) != SVB_OK) return st;
+    return hip_status(timed(c.encode ? "batch_encode" : "batch_decode", s,
+                            [&] { return launch_batch(a, kBatchWork, c.encode, delta, s); }));
 }
 
 // Times each chunk choice on the caller's batch and keeps the fastest.
@@ -354,12 +378,72 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
 
 }  // namespace
 
-// Batched decode for the serving runtime (same path as svb_decode_batch).
-int serve_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
-                       const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
-                       uint64_t total_ints, uint32_t *err, void *stream) {
-    BatchCall c = {false, m, counts, in_off, in_bytes, in, out_off, out, nullptr, starts, total_ints, err};
-    return do_batch(c, 0, stream);
+// Task index of a serving pool: the batched decoder's task table for every
+// list of the pool, built once (descriptors with no output address, the first
+// task of each list).  The caller owns *desc and *lbase (hipFree).  Returns
+// SVB_ERR_INVALID if a list is corrupt (its control stream longer than its
+// bytes) or too long.
+int build_pool_index(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                     const uint8_t *in, const uint32_t *starts, uint64_t total_ints, TaskDesc **desc,
+                     uint32_t **lbase, uint32_t *tasks, hipStream_t s) {
+    *desc = nullptr;
+    *lbase = nullptr;
+    *tasks = 0;
+    BatchCall c = {false, m, counts, in_off, in_bytes, in, nullptr, nullptr, nullptr, starts, total_ints, nullptr};
+    uint64_t T = 0;
+    int st = check_batch(c, true, &T);
+    if (st != SVB_OK || m == 0) return m == 0 ? SVB_ERR_INVALID : st;
+    const BatchLayout L = batch_layout(m, T);
+    uint8_t *sc = nullptr;
+    uint32_t *d_err = nullptr;
+    if (hipMalloc((void **)&sc, L.need) != hipSuccess) return SVB_ERR_NOMEM;
+    if (hipMalloc((void **)&d_err, 4) != hipSuccess) {
+        (void)hipFree(sc);
+        return SVB_ERR_NOMEM;
+    }
+    c.err = d_err;
+    BatchArgs a;
+    uint32_t h_err = 0, h_tasks = 0;
+    st = hip_status(launch_fill(d_err, 1, 0u, s));
+    if (st == SVB_OK) {
+        std::lock_guard<std::mutex> lock(g_mu);
+        st = prepare_batch(c, kDefaultChunk, T, sc, a, s);
+    }
+    if (st == SVB_OK && (hipMemcpyAsync(&h_tasks, a.lbase + m, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+        st = SVB_ERR_HIP;
+    if (st == SVB_OK && (h_err != 0 || h_tasks > T)) st = SVB_ERR_INVALID;
+    if (st == SVB_OK) {
+        if (hipMalloc((void **)desc, 64ull * (h_tasks ? h_tasks : 1)) != hipSuccess ||
+            hipMalloc((void **)lbase, 4ull * (m + 1)) != hipSuccess)
+            st = SVB_ERR_NOMEM;
+        else if (hipMemcpyAsync(*desc, a.desc, 64ull * h_tasks, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                 hipMemcpyAsync(*lbase, a.lbase, 4ull * (m + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                 hipStreamSynchronize(s) != hipSuccess)
+            st = SVB_ERR_HIP;
+    }
+    (void)hipFree(sc);
+    (void)hipFree(d_err);
+    if (st != SVB_OK) {
+        if (*desc) (void)hipFree(*desc);
+        if (*lbase) (void)hipFree(*lbase);
+        *desc = nullptr;
+        *lbase = nullptr;
+        return st;
+    }
+    *tasks = h_tasks;
+    return SVB_OK;
+}
+
+// The walk of a serving batch whose descriptors are in a.desc (tasks
+// a.lbase[a.m]); chunk 0 = the tuned choice for batched decoding.
+int serve_walk(BatchArgs &a, bool delta, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        a.chunk = tuned_chunk(delta ? 1 : 0);
+    }
+    return hip_status(launch_batch(a, kBatchWork, false, delta, s));
 }
 
 }  // namespace svb

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void batch_desc_kernel(BatchArgs a) {
     } else {
         d.in = (uint64_t)(a.in8 + a.in_off[i]);
         d.in_bytes = a.in_bytes[i];
-        d.out = (uint64_t)(a.out32 + a.out_off[i]);
+        d.out = a.out_off ? (uint64_t)(a.out32 + a.out_off[i]) : 0ull;  // none in a task index
     }
     d.n = a.counts[i];
     d.boff = a.ioff[t] - a.ioff[first];
@@ -383,6 +383,30 @@ __global__ __launch_bounds__(kThreads) void batch_encode_kernel(BatchArgs a) {
 uint32_t list_grid(uint32_t m) { return (m + kThreads - 1) / kThreads; }
 uint32_t wave_grid(uint64_t waves) { return (uint32_t)((waves + kWaves - 1) / kWaves); }
 
+// ---------------------------------------------------------------- serving
+
+// One serving batch's descriptors: task t finds its batch list j (base[j] <=
+// t < base[j + 1], a binary search over the batch's small, cache-resident
+// table) and copies the index descriptor of that list's segment t - base[j],
+// pointed at the list's arena range.  One thread per task, so a list's
+// segments are copied in parallel.
+__global__ __launch_bounds__(kThreads) void serve_desc_kernel(ServeDescArgs a) {
+    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t tasks = a.base[a.m];
+    if (t >= tasks) return;
+    uint32_t lo = 0, hi = a.m;  // invariant: base[lo] <= t < base[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.base[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    TaskDesc d = a.pool_desc[a.pool_lbase[a.list[lo]] + (t - a.base[lo])];
+    d.out = (uint64_t)(a.arena + a.out_off[lo]);
+    a.desc[t] = d;
+}
+
 }  // namespace
 
 hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s) {
@@ -436,6 +460,12 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_desc(const ServeDescArgs &a, uint32_t tasks, hipStream_t s) {
+    if (a.m == 0 || tasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(serve_desc_kernel, dim3((tasks + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -109,6 +109,25 @@ enum BatchPhase {
 };
 hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s);
 
+// Serving: the descriptors of one batch, copied from the pool's task index
+// (built once by the batched decoder's preparation passes) with each list's
+// output address in the arena.
+struct ServeDescArgs {
+    uint32_t m;                  // lists in the batch
+    const uint32_t *list;        // pool list of each batch list
+    const uint64_t *out_off;     // arena offset (uint32 units) of each batch list
+    const uint32_t *base;        // first task of each batch list; base[m] = tasks in the batch
+    const TaskDesc *pool_desc;   // task index of the pool (no output addresses)
+    const uint32_t *pool_lbase;  // first index task of each pool list
+    uint32_t *arena;
+    TaskDesc *desc;              // out: the batch's descriptors
+};
+hipError_t launch_serve_desc(const ServeDescArgs &a, uint32_t tasks, hipStream_t s);  // tasks = base[m]
+int build_pool_index(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                     const uint8_t *in, const uint32_t *starts, uint64_t total_ints, TaskDesc **desc,
+                     uint32_t **lbase, uint32_t *tasks, hipStream_t s);
+int serve_walk(BatchArgs &a, bool delta, hipStream_t s);
+
 // Encoding (two passes: data bytes per segment, scan, pack).
 // A stream to encode: n values at `in`; the stream (control bytes first) is
 // written at `out`.  Delta encoding starts from `start`.

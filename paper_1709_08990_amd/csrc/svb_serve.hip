@@ -2,18 +2,26 @@
 // memory, queries of a few lists each, admission by output memory, and
 // continuous batching over the batched decoder.
 //
+// When the server is created, the batched decoder's preparation passes run
+// once over the whole pool and leave its task index: a 64-byte descriptor per
+// segment of every list, holding the segment's byte offset and, for delta
+// coding, the running sum before it.  A query's lists then need no pass over
+// their control bytes before they are decoded.
+//
 // Each query asks for k lists; its result is the k lists decoded back to back
 // into one region of a fixed output arena.  A scheduling step:
 //   1. retires batches whose completion event has fired (their queries become
 //      complete; the caller reads results, then releases them);
 //   2. admits waiting queries in arrival order while the arena has room for
-//      their output (first fit over free ranges; the first query that does not
-//      fit waits, and so does everything behind it);
-//   3. launches one batched decode of every admitted query's lists on a free
-//      stream slot, so batches admitted while others are still on the device
-//      run alongside them.
+//      their output (next fit over coalesced free ranges; the first query that
+//      does not fit waits, and so does everything behind it);
+//   3. launches one batch of every admitted query's lists on a free stream
+//      slot: one copy of the batch table (per list: pool list, first task,
+//      arena offset), one kernel that copies the lists' index descriptors with
+//      their output addresses, and the batched decoder's walk.  Batches
+//      admitted while others are still on the device run alongside them.
 // Host work per step is bookkeeping plus one asynchronous copy of the batch's
-// list table; nothing waits for the device unless the caller asks to block.
+// table; nothing waits for the device unless the caller asks to block.
 #include <algorithm>
 #include <chrono>
 #include <deque>
@@ -24,77 +32,105 @@
 
 #include "svb_internal.hpp"
 
-namespace svb {
-int serve_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
-                       const uint8_t *in, const uint64_t *out_off, uint32_t *out, const uint32_t *starts,
-                       uint64_t total_ints, uint32_t *err, void *stream);
-}
-
 namespace {
 
-using svb::serve_decode_batch;
+using svb::BatchArgs;
+using svb::ServeDescArgs;
+using svb::TaskDesc;
+using svb::kSegInts;
 
+// A query in the server's slab (entries are reused, so their list vectors
+// keep their capacity and a steady stream of queries allocates nothing).
 struct Query {
     uint64_t id;
     std::vector<uint32_t> lists;
     uint64_t ints;       // output integers
+    uint64_t tasks;      // segments to decode
     uint64_t arena_off;  // in integers
     int state;           // 0 waiting, 1 admitted, 2 on the device, 3 complete
+    bool external;       // submitted through svb_server_submit (else by the replay driver)
 };
 
-// One stream slot: a batch in flight and the buffers it owns.
+// One stream slot: a batch in flight and the buffers it owns.  The batch
+// table holds, per batch list, its pool list and arena offset, and the first
+// task of each list (plus the task total).
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
     uint64_t seq = 0;  // launch order of the batch in flight
-    std::vector<uint64_t> queries;
-    uint32_t cap = 0;           // lists the buffers hold
-    uint64_t *h_table = nullptr;  // pinned: counts | in_off | in_bytes | out_off (4 x cap u64) + starts (cap u32)
-    uint64_t *d_table = nullptr;
+    std::vector<uint32_t> queries;  // slab entries of the batch in flight
+    uint32_t cap = 0;             // lists the table holds
+    uint8_t *h_table = nullptr;   // pinned host copy
+    uint8_t *d_table = nullptr;
+    uint64_t task_cap = 0;        // descriptors d_desc holds
+    TaskDesc *d_desc = nullptr;
     uint32_t *d_err = nullptr;
 };
+
+// Table layout for `cap` lists: list ids (u32), task bases (u32, cap + 1),
+// arena offsets (u64, 8-byte aligned).
+size_t table_lists_off(uint32_t) { return 0; }
+size_t table_base_off(uint32_t cap) { return 4ull * cap; }
+size_t table_out_off(uint32_t cap) { return (4ull * cap + 4ull * (cap + 1) + 7) & ~7ull; }
+size_t table_bytes(uint32_t cap) { return table_out_off(cap) + 8ull * cap; }
 
 struct Server {
     int device = 0;
     uint32_t m = 0;
-    std::vector<uint64_t> counts, in_off, in_bytes;  // host copies of the pool table
-    std::vector<uint32_t> starts;
+    std::vector<uint64_t> counts;  // host copy of the pool's list lengths
     bool delta = false;
-    const uint8_t *in = nullptr;
+    TaskDesc *pool_desc = nullptr;  // task index of the pool
+    uint32_t *pool_lbase = nullptr;
     uint32_t *arena = nullptr;
     uint64_t arena_ints = 0;
-    std::map<uint64_t, uint64_t> free_ranges;  // offset -> length (integers)
-    std::deque<uint64_t> waiting;
-    std::vector<uint64_t> admitted;
-    std::unordered_map<uint64_t, Query> queries;
-    std::deque<uint64_t> completed;
+    // Free ranges of the arena (offset -> length, integers), coalesced on
+    // release.  Allocation is next fit: the search starts where the previous
+    // allocation ended, so results admitted in order and released in about
+    // that order find their space at once, and a result held out of order only
+    // leaves a hole that later allocations can still use.
+    std::map<uint64_t, uint64_t> free_ranges;
+    uint64_t rover = 0;
+    std::vector<Query> slab;
+    std::vector<uint32_t> free_entries;
+    std::unordered_map<uint64_t, uint32_t> by_id;  // live queries of svb_server_submit
+    std::deque<uint32_t> waiting, admitted;        // slab entries, arrival order
+    std::deque<uint32_t> completed;                // complete, not polled (svb_server_submit)
+    std::deque<uint32_t> completed_replay;         // complete (replay driver)
     std::vector<Slot> slots;
     uint32_t max_batch_lists = 0;
     uint64_t stats[8] = {};  // batches, lists, integers, queries admitted, queries completed, peak slots busy,
                              // corrupt batches, arena peak integers in use
     uint64_t in_use = 0;
     uint64_t launches = 0;
+    uint64_t steps = 0, slow_steps = 0, max_step_ns = 0;  // host time of scheduling steps (slow: > 1 ms)
     std::mutex mu;
 };
 
 bool arena_alloc(Server &s, uint64_t n, uint64_t *off) {
-    if (n == 0) {
-        *off = 0;
+    *off = 0;
+    if (n == 0) return true;
+    auto take = [&](std::map<uint64_t, uint64_t>::iterator it) {
+        *off = it->first;
+        const uint64_t rest = it->second - n;
+        const uint64_t roff = it->first + n;
+        s.free_ranges.erase(it);
+        if (rest) s.free_ranges.emplace(roff, rest);
+        s.rover = roff;
+        s.in_use += n;
+        s.stats[7] = std::max(s.stats[7], s.in_use);
         return true;
+    };
+    // the range holding the rover, then every range after it, then the ones before
+    auto start = s.free_ranges.upper_bound(s.rover);
+    if (start != s.free_ranges.begin()) {
+        auto prev = std::prev(start);
+        if (prev->first + prev->second > s.rover) start = prev;
     }
-    for (auto it = s.free_ranges.begin(); it != s.free_ranges.end(); ++it) {
-        if (it->second >= n) {
-            *off = it->first;
-            const uint64_t rest = it->second - n;
-            const uint64_t roff = it->first + n;
-            s.free_ranges.erase(it);
-            if (rest) s.free_ranges[roff] = rest;
-            s.in_use += n;
-            s.stats[7] = std::max(s.stats[7], s.in_use);
-            return true;
-        }
-    }
+    for (auto it = start; it != s.free_ranges.end(); ++it)
+        if (it->second >= n) return take(it);
+    for (auto it = s.free_ranges.begin(); it != start; ++it)
+        if (it->second >= n) return take(it);
     return false;
 }
 
@@ -116,19 +152,27 @@ void arena_free(Server &s, uint64_t off, uint64_t n) {
     }
 }
 
-int ensure_slot_capacity(Slot &sl, uint32_t lists) {
-    if (lists <= sl.cap) return SVB_OK;
-    uint32_t cap = std::max<uint32_t>(1024, sl.cap);
-    while (cap < lists) cap *= 2;
-    if (sl.h_table) (void)hipHostFree(sl.h_table);
-    if (sl.d_table) (void)hipFree(sl.d_table);
-    sl.h_table = nullptr;
-    sl.d_table = nullptr;
-    sl.cap = 0;
-    const size_t bytes = (size_t)cap * (4 * sizeof(uint64_t) + sizeof(uint32_t));
-    if (hipHostMalloc((void **)&sl.h_table, bytes, hipHostMallocDefault) != hipSuccess) return SVB_ERR_NOMEM;
-    if (hipMalloc((void **)&sl.d_table, bytes) != hipSuccess) return SVB_ERR_NOMEM;
-    sl.cap = cap;
+int ensure_slot_capacity(Slot &sl, uint32_t lists, uint64_t tasks) {
+    if (lists > sl.cap) {
+        const uint32_t cap = lists;
+        if (sl.h_table) (void)hipHostFree(sl.h_table);
+        if (sl.d_table) (void)hipFree(sl.d_table);
+        sl.h_table = nullptr;
+        sl.d_table = nullptr;
+        sl.cap = 0;
+        if (hipHostMalloc((void **)&sl.h_table, table_bytes(cap), hipHostMallocDefault) != hipSuccess)
+            return SVB_ERR_NOMEM;
+        if (hipMalloc((void **)&sl.d_table, table_bytes(cap)) != hipSuccess) return SVB_ERR_NOMEM;
+        sl.cap = cap;
+    }
+    if (tasks > sl.task_cap) {
+        const uint64_t cap = tasks;
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
+        sl.d_desc = nullptr;
+        sl.task_cap = 0;
+        if (hipMalloc((void **)&sl.d_desc, sizeof(TaskDesc) * cap) != hipSuccess) return SVB_ERR_NOMEM;
+        sl.task_cap = cap;
+    }
     return SVB_OK;
 }
 
@@ -141,9 +185,9 @@ int retire(Server &s, bool block) {
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) return SVB_ERR_HIP;
-            for (uint64_t id : sl.queries) {
-                s.queries[id].state = 3;
-                s.completed.push_back(id);
+            for (uint32_t e : sl.queries) {
+                s.slab[e].state = 3;
+                (s.slab[e].external ? s.completed : s.completed_replay).push_back(e);
                 s.stats[4]++;
             }
             sl.queries.clear();
@@ -163,12 +207,13 @@ int retire(Server &s, bool block) {
 
 void admit(Server &s) {
     while (!s.waiting.empty()) {
-        Query &q = s.queries[s.waiting.front()];
+        const uint32_t e = s.waiting.front();
+        Query &q = s.slab[e];
         uint64_t off;
         if (!arena_alloc(s, q.ints, &off)) break;
         q.arena_off = off;
         q.state = 1;
-        s.admitted.push_back(q.id);
+        s.admitted.push_back(e);
         s.waiting.pop_front();
         s.stats[3]++;
     }
@@ -186,46 +231,60 @@ int launch(Server &s) {
     // take admitted queries in order while their lists fit the batch limit
     size_t take = 0;
     uint32_t lists = 0;
+    uint64_t tasks = 0;
     while (take < s.admitted.size()) {
-        const uint32_t k = (uint32_t)s.queries[s.admitted[take]].lists.size();
+        const Query &q = s.slab[s.admitted[take]];
+        const uint32_t k = (uint32_t)q.lists.size();
         if (take > 0 && lists + k > s.max_batch_lists) break;
         lists += k;
+        tasks += q.tasks;
         ++take;
     }
-    int st = ensure_slot_capacity(*slot, lists);
+    int st = ensure_slot_capacity(*slot, lists, tasks);
     if (st != SVB_OK) return st;
     const uint32_t cap = slot->cap;
-    uint64_t *h_counts = slot->h_table, *h_in_off = h_counts + cap, *h_in_bytes = h_in_off + cap,
-             *h_out_off = h_in_bytes + cap;
-    uint32_t *h_starts = (uint32_t *)(h_out_off + cap);
-    uint32_t j = 0;
+    uint32_t *h_list = (uint32_t *)(slot->h_table + table_lists_off(cap));
+    uint32_t *h_base = (uint32_t *)(slot->h_table + table_base_off(cap));
+    uint64_t *h_out = (uint64_t *)(slot->h_table + table_out_off(cap));
+    uint32_t j = 0, t = 0;
     uint64_t total = 0;
     slot->queries.assign(s.admitted.begin(), s.admitted.begin() + take);
-    for (uint64_t id : slot->queries) {
-        Query &q = s.queries[id];
+    for (uint32_t e : slot->queries) {
+        Query &q = s.slab[e];
         uint64_t o = q.arena_off;
         for (uint32_t list : q.lists) {
-            h_counts[j] = s.counts[list];
-            h_in_off[j] = s.in_off[list];
-            h_in_bytes[j] = s.in_bytes[list];
-            h_out_off[j] = o;
-            h_starts[j] = s.delta ? s.starts[list] : 0u;
+            h_list[j] = list;
+            h_base[j] = t;
+            h_out[j] = o;
             o += s.counts[list];
             total += s.counts[list];
+            t += (uint32_t)((s.counts[list] + kSegInts - 1) / kSegInts);
             ++j;
         }
         q.state = 2;
     }
+    h_base[j] = t;
     s.admitted.erase(s.admitted.begin(), s.admitted.begin() + take);
-    const size_t bytes = (size_t)cap * (4 * sizeof(uint64_t) + sizeof(uint32_t));
-    if (hipMemcpyAsync(slot->d_table, slot->h_table, bytes, hipMemcpyHostToDevice, slot->stream) != hipSuccess)
+    if (hipMemcpyAsync(slot->d_table, slot->h_table, table_bytes(cap), hipMemcpyHostToDevice, slot->stream) !=
+        hipSuccess)
         return SVB_ERR_HIP;
-    uint64_t *d_counts = slot->d_table, *d_in_off = d_counts + cap, *d_in_bytes = d_in_off + cap,
-             *d_out_off = d_in_bytes + cap;
-    uint32_t *d_starts = (uint32_t *)(d_out_off + cap);
-    st = serve_decode_batch(j, d_counts, d_in_off, d_in_bytes, s.in, d_out_off, s.arena, s.delta ? d_starts : nullptr,
-                            total, slot->d_err, slot->stream);
-    if (st != SVB_OK) return st;
+    ServeDescArgs d;
+    d.m = j;
+    d.list = (const uint32_t *)(slot->d_table + table_lists_off(cap));
+    d.base = (const uint32_t *)(slot->d_table + table_base_off(cap));
+    d.out_off = (const uint64_t *)(slot->d_table + table_out_off(cap));
+    d.pool_desc = s.pool_desc;
+    d.pool_lbase = s.pool_lbase;
+    d.arena = s.arena;
+    d.desc = slot->d_desc;
+    if (svb::launch_serve_desc(d, t, slot->stream) != hipSuccess) return SVB_ERR_HIP;
+    BatchArgs a = {};
+    a.m = j;
+    a.lbase = (uint32_t *)d.base;
+    a.t_cap = t;
+    a.desc = slot->d_desc;
+    a.err = slot->d_err;
+    if (t && (st = svb::serve_walk(a, s.delta, slot->stream)) != SVB_OK) return st;
     if (hipEventRecord(slot->done, slot->stream) != hipSuccess) return SVB_ERR_HIP;
     slot->busy = true;
     slot->seq = s.launches++;
@@ -238,31 +297,65 @@ int launch(Server &s) {
     return SVB_OK;
 }
 
-int submit_locked(Server &s, uint64_t query_id, uint32_t k, const uint32_t *list_ids) {
-    if (s.queries.count(query_id)) return SVB_ERR_INVALID;
-    Query q;
+// Queues a query; `external` ones are registered under their id for
+// svb_server_poll / svb_server_release.  *entry receives its slab entry.
+int submit_locked(Server &s, uint64_t query_id, uint32_t k, const uint32_t *list_ids, bool external,
+                  uint32_t *entry) {
+    if (external && s.by_id.count(query_id)) return SVB_ERR_INVALID;
+    if (k > s.max_batch_lists) return SVB_ERR_INVALID;  // could never be admitted
+    uint64_t ints = 0, tasks = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        const uint32_t l = list_ids[i];
+        if (l >= s.m) return SVB_ERR_INVALID;
+        ints += s.counts[l];
+        tasks += (s.counts[l] + kSegInts - 1) / kSegInts;
+    }
+    if (ints > s.arena_ints) return SVB_ERR_INVALID;
+    uint32_t e;
+    if (!s.free_entries.empty()) {
+        e = s.free_entries.back();
+        s.free_entries.pop_back();
+    } else {
+        e = (uint32_t)s.slab.size();
+        s.slab.emplace_back();
+    }
+    Query &q = s.slab[e];
     q.id = query_id;
     q.lists.assign(list_ids, list_ids + k);
-    q.ints = 0;
-    for (uint32_t l : q.lists) {
-        if (l >= s.m) return SVB_ERR_INVALID;
-        q.ints += s.counts[l];
-    }
-    if (q.ints > s.arena_ints || k > s.max_batch_lists) return SVB_ERR_INVALID;  // could never be admitted
+    q.ints = ints;
+    q.tasks = tasks;
     q.arena_off = 0;
     q.state = 0;
-    s.queries.emplace(query_id, std::move(q));
-    s.waiting.push_back(query_id);
+    q.external = external;
+    if (external) s.by_id.emplace(query_id, e);
+    s.waiting.push_back(e);
+    if (entry) *entry = e;
     return SVB_OK;
 }
 
-// One scheduling step (see svb_server_step).
-int step_locked(Server &s, bool block) {
+// Frees a complete query's arena range and slab entry.
+void finish_query(Server &s, uint32_t e) {
+    Query &q = s.slab[e];
+    arena_free(s, q.arena_off, q.ints);
+    if (q.external) s.by_id.erase(q.id);
+    q.state = -1;
+    s.free_entries.push_back(e);
+}
+
+// One scheduling step (see svb_server_step).  With block, waits for a batch
+// if `watch` (a completion queue) is empty.
+int step_locked(Server &s, bool block, const std::deque<uint32_t> &watch) {
+    typedef std::chrono::steady_clock clock;
+    const clock::time_point t0 = clock::now();
     int st = retire(s, false);
     if (st != SVB_OK) return st;
     admit(s);
     if ((st = launch(s)) != SVB_OK) return st;
-    if (block && s.completed.empty()) {
+    const uint64_t ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(clock::now() - t0).count();
+    s.steps++;
+    if (ns > 1000000) s.slow_steps++;
+    s.max_step_ns = std::max(s.max_step_ns, ns);
+    if (block && watch.empty()) {
         if ((st = retire(s, true)) != SVB_OK) return st;
         admit(s);
         if ((st = launch(s)) != SVB_OK) return st;
@@ -279,9 +372,12 @@ void destroy(Server *s) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.h_table) (void)hipHostFree(sl.h_table);
         if (sl.d_table) (void)hipFree(sl.d_table);
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
         if (sl.d_err) (void)hipFree(sl.d_err);
     }
     if (s->arena) (void)hipFree(s->arena);
+    if (s->pool_desc) (void)hipFree(s->pool_desc);
+    if (s->pool_lbase) (void)hipFree(s->pool_lbase);
     delete s;
 }
 
@@ -299,22 +395,17 @@ int svb_server_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off
     (void)hipGetDevice(&s->device);
     s->m = m;
     s->counts.resize(m);
-    s->in_off.resize(m);
-    s->in_bytes.resize(m);
     s->delta = starts != nullptr;
     int st = SVB_OK;
-    if (hipMemcpy(s->counts.data(), counts, 8ull * m, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(s->in_off.data(), in_off, 8ull * m, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(s->in_bytes.data(), in_bytes, 8ull * m, hipMemcpyDeviceToHost) != hipSuccess)
-        st = SVB_ERR_HIP;
-    if (st == SVB_OK && s->delta) {
-        s->starts.resize(m);
-        if (hipMemcpy(s->starts.data(), starts, 4ull * m, hipMemcpyDeviceToHost) != hipSuccess) st = SVB_ERR_HIP;
+    if (hipMemcpy(s->counts.data(), counts, 8ull * m, hipMemcpyDeviceToHost) != hipSuccess) st = SVB_ERR_HIP;
+    uint64_t total = 0, tasks = 0;
+    for (uint64_t c : s->counts) {
+        total += c;
+        tasks += (c + kSegInts - 1) / kSegInts;
     }
-    s->in = in;
     s->arena_ints = arena_bytes / 4;
     if (st == SVB_OK && hipMalloc((void **)&s->arena, s->arena_ints * 4) != hipSuccess) st = SVB_ERR_NOMEM;
-    if (st == SVB_OK) s->free_ranges[0] = s->arena_ints;
+    if (st == SVB_OK) s->free_ranges.emplace(0, s->arena_ints);
     s->max_batch_lists = max_batch_lists;
     s->slots.resize(streams);
     for (Slot &sl : s->slots) {
@@ -324,6 +415,20 @@ int svb_server_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off
             hipMalloc((void **)&sl.d_err, 4) != hipSuccess || hipMemset(sl.d_err, 0, 4) != hipSuccess)
             st = SVB_ERR_HIP;
     }
+    // each slot's table and descriptors at their largest (a batch holds at
+    // most max_batch_lists lists and an arena's worth of integers), so no
+    // allocation ever happens between batches
+    for (Slot &sl : s->slots) {
+        if (st != SVB_OK) break;
+        st = ensure_slot_capacity(sl, max_batch_lists, (uint64_t)max_batch_lists + s->arena_ints / kSegInts + 1);
+    }
+    // the pool's task index: byte offset and carry of every segment of every
+    // list, computed once; a corrupt or oversized list refuses the pool
+    uint32_t index_tasks = 0;
+    if (st == SVB_OK)
+        st = svb::build_pool_index(m, counts, in_off, in_bytes, in, starts, total, &s->pool_desc, &s->pool_lbase,
+                                   &index_tasks, s->slots[0].stream);
+    if (st == SVB_OK && index_tasks != tasks) st = SVB_ERR_INVALID;
     if (st != SVB_OK) {
         destroy(s);
         return st;
@@ -336,7 +441,7 @@ int svb_server_submit(void *server, uint64_t query_id, uint32_t k, const uint32_
     Server *s = (Server *)server;
     if (!s || k == 0 || !list_ids) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
-    return submit_locked(*s, query_id, k, list_ids);
+    return submit_locked(*s, query_id, k, list_ids, true, nullptr);
 }
 
 int svb_server_step(void *server, int block) {
@@ -344,7 +449,7 @@ int svb_server_step(void *server, int block) {
     if (!s) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
     (void)hipSetDevice(s->device);
-    const int st = step_locked(*s, block != 0);
+    const int st = step_locked(*s, block != 0, s->completed);
     if (st != SVB_OK) return st;
     return (int)std::min<size_t>(s->completed.size(), 1u << 30);
 }
@@ -355,10 +460,9 @@ int svb_server_poll(void *server, uint64_t *ids, uint64_t *arena_off, uint64_t *
     std::lock_guard<std::mutex> lock(s->mu);
     uint32_t n = 0;
     while (n < cap && !s->completed.empty()) {
-        const uint64_t id = s->completed.front();
+        const Query &q = s->slab[s->completed.front()];
         s->completed.pop_front();
-        const Query &q = s->queries[id];
-        ids[n] = id;
+        ids[n] = q.id;
         arena_off[n] = q.arena_off;
         ints[n] = q.ints;
         ++n;
@@ -370,28 +474,25 @@ int svb_server_release(void *server, uint64_t query_id) {
     Server *s = (Server *)server;
     if (!s) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
-    auto it = s->queries.find(query_id);
-    if (it == s->queries.end() || it->second.state != 3) return SVB_ERR_INVALID;
-    arena_free(*s, it->second.arena_off, it->second.ints);
-    s->queries.erase(it);
+    auto it = s->by_id.find(query_id);
+    if (it == s->by_id.end() || s->slab[it->second].state != 3) return SVB_ERR_INVALID;
+    finish_query(*s, it->second);
     return SVB_OK;
 }
 
 int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
-                      uint32_t outstanding, uint64_t id_base, double *latency_s, double *wall_s) {
+                      uint32_t outstanding, double *latency_s, double *wall_s) {
     Server *s = (Server *)server;
     if (!s || !qoff || (nq && (!lists || !latency_s)) || (!arrival_s && outstanding == 0)) return SVB_ERR_INVALID;
     for (uint64_t i = 0; i < nq; ++i)
         if (qoff[i + 1] <= qoff[i] || qoff[i + 1] - qoff[i] > 0xFFFFFFFFull) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
     (void)hipSetDevice(s->device);
-    for (uint64_t i = 0; i < nq; ++i)
-        if (s->queries.count(id_base + i)) return SVB_ERR_INVALID;
+    if (!s->completed_replay.empty()) return SVB_ERR_INVALID;  // a previous replay did not finish
     typedef std::chrono::steady_clock clock;
     const clock::time_point t0 = clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
     std::vector<double> sent(nq, 0.0);
-    std::vector<uint64_t> other;  // completions of queries submitted outside this replay stay pollable
     uint64_t next = 0, done = 0;
     int st = SVB_OK;
     while (done < nq) {
@@ -399,34 +500,28 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
         const double t = now_s();
         while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding)) {
             sent[next] = arrival_s ? arrival_s[next] : t;
-            st = submit_locked(*s, id_base + next, (uint32_t)(qoff[next + 1] - qoff[next]), lists + qoff[next]);
+            // the query's id is its index in the trace (replayed queries are not pollable)
+            st = submit_locked(*s, next, (uint32_t)(qoff[next + 1] - qoff[next]), lists + qoff[next], false, nullptr);
             if (st != SVB_OK) return st;
             ++next;
         }
         // closed loop: nothing else can happen until a batch finishes, so wait for one
         const bool block = !arrival_s && next - done >= outstanding;
-        if ((st = step_locked(*s, block)) != SVB_OK) return st;
-        if (s->completed.empty() && !s->waiting.empty() && s->admitted.empty() &&
+        if ((st = step_locked(*s, block, s->completed_replay)) != SVB_OK) return st;
+        if (s->completed_replay.empty() && !s->waiting.empty() && s->admitted.empty() &&
             std::none_of(s->slots.begin(), s->slots.end(), [](const Slot &sl) { return sl.busy; }))
             return SVB_ERR_NOMEM;  // nothing on the device and the arena is held by unreleased results
-        if (!s->completed.empty()) {
+        if (!s->completed_replay.empty()) {
             const double tc = now_s();
-            while (!s->completed.empty()) {
-                const uint64_t id = s->completed.front();
-                s->completed.pop_front();
-                auto it = s->queries.find(id);
-                if (id >= id_base && id - id_base < nq) {
-                    latency_s[id - id_base] = tc - sent[id - id_base];
-                    arena_free(*s, it->second.arena_off, it->second.ints);
-                    s->queries.erase(it);
-                    ++done;
-                } else {
-                    other.push_back(id);
-                }
+            while (!s->completed_replay.empty()) {
+                const uint32_t e = s->completed_replay.front();
+                s->completed_replay.pop_front();
+                latency_s[s->slab[e].id] = tc - sent[s->slab[e].id];
+                finish_query(*s, e);
+                ++done;
             }
         }
     }
-    for (uint64_t id : other) s->completed.push_back(id);
     if (wall_s) *wall_s = now_s();
     return SVB_OK;
 }
@@ -443,8 +538,9 @@ int svb_server_stats(void *server, uint64_t *out, uint32_t cap) {
         if (!sl.busy && hipMemcpy(&e, sl.d_err, 4, hipMemcpyDeviceToHost) == hipSuccess) err |= e;
     }
     s->stats[6] = err;
-    const uint64_t extra[3] = {(uint64_t)s->waiting.size(), (uint64_t)s->admitted.size(), s->in_use};
-    for (uint32_t i = 0; i < cap; ++i) out[i] = i < 8 ? s->stats[i] : (i < 11 ? extra[i - 8] : 0);
+    const uint64_t extra[6] = {(uint64_t)s->waiting.size(), (uint64_t)s->admitted.size(), s->in_use,
+                               s->steps, s->slow_steps, s->max_step_ns / 1000};
+    for (uint32_t i = 0; i < cap; ++i) out[i] = i < 8 ? s->stats[i] : (i < 14 ? extra[i - 8] : 0);
     return SVB_OK;
 }
 

@@ -42,10 +42,10 @@ class Server:
     def stats(self):
         return svb_server_stats(self.handle)
 
-    def replay(self, picks, arrivals=None, outstanding=0, id_base=1 << 62):
+    def replay(self, picks, arrivals=None, outstanding=0):
         """Native load generator: open loop at ``arrivals`` or closed loop with ``outstanding``
         queries in flight; results are released unread.  Returns (latencies, wall seconds)."""
-        return svb_server_replay(self.handle, picks, arrivals, outstanding, id_base)
+        return svb_server_replay(self.handle, picks, arrivals, outstanding)
 
     def close(self):
         if self.handle:

@@ -128,15 +128,27 @@ def test_replay_open_and_closed_loop():
     server = serve.Server(dev["counts"], dev["in_off"], dev["in_bytes"], dev["streams"], dev["starts"],
                           arena_bytes=4 << 20, slots=4, max_batch_lists=512)
     times, qoff, ids = inputs.poisson_queries_flat(3_000, 20_000.0, len(lists), seed=92)
+    # queries of the ordinary interface, queued before the replay, ride along in its batches
+    mine = {100 + q: ids[qoff[q]:qoff[q + 1]] for q in range(5)}
+    for qid, p in mine.items():
+        server.submit(qid, p)
     log_case("serve replay open loop")
     lat, wall = server.replay((qoff, ids), arrivals=times)
+    got = {}
+    while len(got) < len(mine):
+        server.step(block=True)
+        for qid, off, n in server.poll():
+            got[qid] = read_result(server, off, n)
+            server.release(qid)
+    for qid, p in mine.items():
+        np.testing.assert_array_equal(got[qid], expected(lists, starts, True, p), err_msg="query %d" % qid)
     assert lat.size == 3_000 and np.all(lat > 0) and wall >= times[-1]
     log_case("serve replay closed loop")
     lat2, _ = server.replay((qoff, ids), outstanding=64)
     assert lat2.size == 3_000 and np.all(lat2 > 0)
     st = server.stats()
-    assert st["completed"] == 6_000 and st["err"] == 0 and st["arena_in_use_ints"] == 0
-    assert st["integers"] == 2 * int(counts[ids].sum())
+    assert st["completed"] == 6_005 and st["err"] == 0 and st["arena_in_use_ints"] == 0
+    assert st["integers"] == 2 * int(counts[ids].sum()) + sum(int(counts[p].sum()) for p in mine.values())
     # the server still answers ordinary queries afterwards, correctly
     p = ids[qoff[5]:qoff[6]]
     server.submit(7, p)
