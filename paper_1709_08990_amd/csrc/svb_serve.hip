@@ -39,11 +39,19 @@ using svb::ServeDescArgs;
 using svb::TaskDesc;
 using svb::kSegInts;
 
-// A query in the server's slab (entries are reused, so their list vectors
-// keep their capacity and a steady stream of queries allocates nothing).
+// A query in the server's slab.  Up to kInlineLists lists are kept in the
+// entry itself, so a waiting query costs no heap allocation however long the
+// queue grows; longer queries spill into vectors.  Entries are reused.
+constexpr uint32_t kInlineLists = 8;
 struct Query {
     uint64_t id;
-    std::vector<uint32_t> lists;
+    uint32_t k;                               // lists
+    uint32_t small_lists[kInlineLists];
+    uint64_t small_counts[kInlineLists];      // integers of each list (read once, at submission)
+    std::vector<uint32_t> big_lists;
+    std::vector<uint64_t> big_counts;
+    uint32_t list(uint32_t i) const { return k <= kInlineLists ? small_lists[i] : big_lists[i]; }
+    uint64_t count(uint32_t i) const { return k <= kInlineLists ? small_counts[i] : big_counts[i]; }
     uint64_t ints;       // output integers
     uint64_t tasks;      // segments to decode
     uint64_t arena_off;  // in integers
@@ -68,8 +76,9 @@ struct Slot {
     uint32_t *d_err = nullptr;
 };
 
-// Table layout for `cap` lists: list ids (u32), task bases (u32, cap + 1),
-// arena offsets (u64, 8-byte aligned).
+// Table layout for a batch of `cap` lists, packed so that one copy of
+// table_bytes(lists) moves exactly the batch's entries: list ids (u32), task
+// bases (u32, lists + 1), arena offsets (u64, 8-byte aligned).
 size_t table_lists_off(uint32_t) { return 0; }
 size_t table_base_off(uint32_t cap) { return 4ull * cap; }
 size_t table_out_off(uint32_t cap) { return (4ull * cap + 4ull * (cap + 1) + 7) & ~7ull; }
@@ -91,7 +100,9 @@ struct Server {
     // leaves a hole that later allocations can still use.
     std::map<uint64_t, uint64_t> free_ranges;
     uint64_t rover = 0;
-    std::vector<Query> slab;
+    uint64_t free_ints = 0;      // sum of the free ranges
+    bool admit_blocked = false;  // the front query did not fit, and nothing was released since
+    std::deque<Query> slab;  // entries never move as it grows
     std::vector<uint32_t> free_entries;
     std::unordered_map<uint64_t, uint32_t> by_id;  // live queries of svb_server_submit
     std::deque<uint32_t> waiting, admitted;        // slab entries, arrival order
@@ -107,36 +118,27 @@ struct Server {
     std::mutex mu;
 };
 
-bool arena_alloc(Server &s, uint64_t n, uint64_t *off) {
-    *off = 0;
-    if (n == 0) return true;
-    auto take = [&](std::map<uint64_t, uint64_t>::iterator it) {
-        *off = it->first;
-        const uint64_t rest = it->second - n;
-        const uint64_t roff = it->first + n;
-        s.free_ranges.erase(it);
-        if (rest) s.free_ranges.emplace(roff, rest);
-        s.rover = roff;
-        s.in_use += n;
-        s.stats[7] = std::max(s.stats[7], s.in_use);
-        return true;
-    };
-    // the range holding the rover, then every range after it, then the ones before
+// Next fit: the free range holding the rover (or the first after it, then
+// the first from the start) that has room for n; end() if none.
+std::map<uint64_t, uint64_t>::iterator arena_find(Server &s, uint64_t n) {
+    if (n > s.free_ints) return s.free_ranges.end();
     auto start = s.free_ranges.upper_bound(s.rover);
     if (start != s.free_ranges.begin()) {
         auto prev = std::prev(start);
         if (prev->first + prev->second > s.rover) start = prev;
     }
     for (auto it = start; it != s.free_ranges.end(); ++it)
-        if (it->second >= n) return take(it);
+        if (it->second >= n) return it;
     for (auto it = s.free_ranges.begin(); it != start; ++it)
-        if (it->second >= n) return take(it);
-    return false;
+        if (it->second >= n) return it;
+    return s.free_ranges.end();
 }
 
 void arena_free(Server &s, uint64_t off, uint64_t n) {
     if (n == 0) return;
     s.in_use -= n;
+    s.free_ints += n;
+    s.admit_blocked = false;
     auto it = s.free_ranges.emplace(off, n).first;
     auto next = std::next(it);
     if (next != s.free_ranges.end() && it->first + it->second == next->first) {
@@ -205,17 +207,44 @@ int retire(Server &s, bool block) {
     return SVB_OK;
 }
 
+// Admits waiting queries in arrival order.  Consecutive queries are carved
+// out of one free range one after the other, so the free-range map changes
+// once per range, not once per query.
 void admit(Server &s) {
+    if (s.admit_blocked) return;  // the arena has not changed since the front query failed to fit
     while (!s.waiting.empty()) {
-        const uint32_t e = s.waiting.front();
-        Query &q = s.slab[e];
-        uint64_t off;
-        if (!arena_alloc(s, q.ints, &off)) break;
-        q.arena_off = off;
-        q.state = 1;
-        s.admitted.push_back(e);
-        s.waiting.pop_front();
-        s.stats[3]++;
+        auto it = s.free_ranges.end();
+        if (s.slab[s.waiting.front()].ints) {
+            it = arena_find(s, s.slab[s.waiting.front()].ints);
+            if (it == s.free_ranges.end()) {
+                s.admit_blocked = true;
+                break;
+            }
+        }
+        const uint64_t off = it == s.free_ranges.end() ? 0 : it->first;
+        const uint64_t end = it == s.free_ranges.end() ? 0 : it->first + it->second;
+        uint64_t pos = off;
+        // the front query fits; so may the ones behind it
+        while (!s.waiting.empty()) {
+            const uint32_t e = s.waiting.front();
+            Query &q = s.slab[e];
+            if (q.ints > end - pos) break;
+            q.arena_off = q.ints ? pos : 0;
+            pos += q.ints;
+            q.state = 1;
+            s.admitted.push_back(e);
+            s.waiting.pop_front();
+            s.stats[3]++;
+            if (it == s.free_ranges.end() && !s.waiting.empty() && s.slab[s.waiting.front()].ints) break;
+        }
+        if (it != s.free_ranges.end()) {
+            s.free_ranges.erase(it);
+            if (end > pos) s.free_ranges.emplace(pos, end - pos);
+            s.rover = pos;
+            s.free_ints -= pos - off;
+            s.in_use += pos - off;
+            s.stats[7] = std::max(s.stats[7], s.in_use);
+        }
     }
 }
 
@@ -234,7 +263,7 @@ int launch(Server &s) {
     uint64_t tasks = 0;
     while (take < s.admitted.size()) {
         const Query &q = s.slab[s.admitted[take]];
-        const uint32_t k = (uint32_t)q.lists.size();
+        const uint32_t k = q.k;
         if (take > 0 && lists + k > s.max_batch_lists) break;
         lists += k;
         tasks += q.tasks;
@@ -242,7 +271,7 @@ int launch(Server &s) {
     }
     int st = ensure_slot_capacity(*slot, lists, tasks);
     if (st != SVB_OK) return st;
-    const uint32_t cap = slot->cap;
+    const uint32_t cap = lists;  // the table is laid out for exactly this batch
     uint32_t *h_list = (uint32_t *)(slot->h_table + table_lists_off(cap));
     uint32_t *h_base = (uint32_t *)(slot->h_table + table_base_off(cap));
     uint64_t *h_out = (uint64_t *)(slot->h_table + table_out_off(cap));
@@ -252,15 +281,17 @@ int launch(Server &s) {
     for (uint32_t e : slot->queries) {
         Query &q = s.slab[e];
         uint64_t o = q.arena_off;
-        for (uint32_t list : q.lists) {
-            h_list[j] = list;
+        const uint32_t k = q.k;
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint64_t c = q.count(i);
+            h_list[j] = q.list(i);
             h_base[j] = t;
             h_out[j] = o;
-            o += s.counts[list];
-            total += s.counts[list];
-            t += (uint32_t)((s.counts[list] + kSegInts - 1) / kSegInts);
+            o += c;
+            t += (uint32_t)((c + kSegInts - 1) / kSegInts);
             ++j;
         }
+        total += q.ints;
         q.state = 2;
     }
     h_base[j] = t;
@@ -303,14 +334,8 @@ int submit_locked(Server &s, uint64_t query_id, uint32_t k, const uint32_t *list
                   uint32_t *entry) {
     if (external && s.by_id.count(query_id)) return SVB_ERR_INVALID;
     if (k > s.max_batch_lists) return SVB_ERR_INVALID;  // could never be admitted
-    uint64_t ints = 0, tasks = 0;
-    for (uint32_t i = 0; i < k; ++i) {
-        const uint32_t l = list_ids[i];
-        if (l >= s.m) return SVB_ERR_INVALID;
-        ints += s.counts[l];
-        tasks += (s.counts[l] + kSegInts - 1) / kSegInts;
-    }
-    if (ints > s.arena_ints) return SVB_ERR_INVALID;
+    for (uint32_t i = 0; i < k; ++i)
+        if (list_ids[i] >= s.m) return SVB_ERR_INVALID;
     uint32_t e;
     if (!s.free_entries.empty()) {
         e = s.free_entries.back();
@@ -321,7 +346,28 @@ int submit_locked(Server &s, uint64_t query_id, uint32_t k, const uint32_t *list
     }
     Query &q = s.slab[e];
     q.id = query_id;
-    q.lists.assign(list_ids, list_ids + k);
+    q.k = k;
+    uint32_t *ql = q.small_lists;
+    uint64_t *qc = q.small_counts;
+    if (k > kInlineLists) {
+        q.big_lists.resize(k);
+        q.big_counts.resize(k);
+        ql = q.big_lists.data();
+        qc = q.big_counts.data();
+    }
+    uint64_t ints = 0, tasks = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        const uint64_t c = s.counts[list_ids[i]];
+        ql[i] = list_ids[i];
+        qc[i] = c;
+        ints += c;
+        tasks += (c + kSegInts - 1) / kSegInts;
+    }
+    if (ints > s.arena_ints) {  // could never be admitted
+        q.state = -1;
+        s.free_entries.push_back(e);
+        return SVB_ERR_INVALID;
+    }
     q.ints = ints;
     q.tasks = tasks;
     q.arena_off = 0;
@@ -405,7 +451,10 @@ int svb_server_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off
     }
     s->arena_ints = arena_bytes / 4;
     if (st == SVB_OK && hipMalloc((void **)&s->arena, s->arena_ints * 4) != hipSuccess) st = SVB_ERR_NOMEM;
-    if (st == SVB_OK) s->free_ranges.emplace(0, s->arena_ints);
+    if (st == SVB_OK) {
+        s->free_ranges.emplace(0, s->arena_ints);
+        s->free_ints = s->arena_ints;
+    }
     s->max_batch_lists = max_batch_lists;
     s->slots.resize(streams);
     for (Slot &sl : s->slots) {
@@ -513,13 +562,29 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
             return SVB_ERR_NOMEM;  // nothing on the device and the arena is held by unreleased results
         if (!s->completed_replay.empty()) {
             const double tc = now_s();
+            // release in completion order, merging ranges that adjoin (a batch's
+            // queries were admitted one after the other), so the free-range map
+            // changes about once per batch
+            uint64_t run_off = 0, run_len = 0;
             while (!s->completed_replay.empty()) {
                 const uint32_t e = s->completed_replay.front();
                 s->completed_replay.pop_front();
-                latency_s[s->slab[e].id] = tc - sent[s->slab[e].id];
-                finish_query(*s, e);
+                Query &q = s->slab[e];
+                latency_s[q.id] = tc - sent[q.id];
+                if (q.ints) {
+                    if (run_len && run_off + run_len == q.arena_off) {
+                        run_len += q.ints;
+                    } else {
+                        arena_free(*s, run_off, run_len);
+                        run_off = q.arena_off;
+                        run_len = q.ints;
+                    }
+                }
+                q.state = -1;
+                s->free_entries.push_back(e);
                 ++done;
             }
+            arena_free(*s, run_off, run_len);
         }
     }
     if (wall_s) *wall_s = now_s();
