@@ -17,6 +17,20 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(4)));
 // Same with natural 16-byte alignment (LDS).
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4)));
 
+// Global-memory views of pointers.  A pointer read out of memory (a batched
+// call's task descriptor) is generic to the compiler, and generic accesses
+// become FLAT instructions, which the LDS wait counter also tracks: every wait
+// before an LDS read would then wait for the next task's prefetched loads
+// too.  Every stream and output access goes through these views.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 constexpr int kWave = 64;
 constexpr int kThreads = 256;           // 4 waves per workgroup
 constexpr int kWaves = kThreads / kWave;

@@ -43,12 +43,12 @@ __device__ __forceinline__ SegCtrl load_seg_ctrl(const DecodeArgs &p, uint64_t s
     if (segment_full(p, s)) {
         // all 256 control bytes lie below ceil(n/4) <= in_bytes
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) r.c[k] = cp[kWave * k];
+        for (uint32_t k = 0; k < 4; ++k) r.c[k] = gptr(cp)[kWave * k];
     } else {
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
             const uint32_t m = block_ints(p, s, k, lane);
-            r.c[k] = m ? (cp[kWave * k] & ((1u << (2 * m)) - 1u)) : 0u;
+            r.c[k] = m ? (gptr(cp)[kWave * k] & ((1u << (2 * m)) - 1u)) : 0u;
         }
     }
     return r;
@@ -101,7 +101,7 @@ __device__ __forceinline__ void span_load(const DecodeArgs &p, Span &sp, uint32_
         const uint32_t c = lane + kWave * i;
         const uint8_t *cp = sp.abase + 16 * c;
         sp.w[i] = u32x4a{0u, 0u, 0u, 0u};
-        if (c < sp.nch && cp < hi && cp + 16 > p.in) sp.w[i] = *(const u32x4a *)cp;
+        if (c < sp.nch && cp < hi && cp + 16 > p.in) sp.w[i] = *gptr((const u32x4a *)cp);
     }
 }
 
@@ -251,7 +251,7 @@ __device__ __forceinline__ void store_segment(const DecodeArgs &p, uint64_t s, u
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k)
             __builtin_nontemporal_store(u32x4{v[k][0] + add, v[k][1] + add, v[k][2] + add, v[k][3] + add},
-                                        (u32x4 *)(o + 4 * kWave * k));
+                                        gptr((u32x4 *)(o + 4 * kWave * k)));
     } else {
         // whole blocks of a partial segment still take one 16-byte store
 #pragma unroll
@@ -260,11 +260,11 @@ __device__ __forceinline__ void store_segment(const DecodeArgs &p, uint64_t s, u
             uint32_t *ok = o + 4 * kWave * k;
             if (m == 4) {
                 __builtin_nontemporal_store(u32x4{v[k][0] + add, v[k][1] + add, v[k][2] + add, v[k][3] + add},
-                                            (u32x4 *)ok);
+                                            gptr((u32x4 *)ok));
             } else {
 #pragma unroll
                 for (uint32_t j = 0; j < 3; ++j)
-                    if (j < m) ok[j] = v[k][j] + add;
+                    if (j < m) gptr(ok)[j] = v[k][j] + add;
             }
         }
     }
@@ -294,10 +294,10 @@ __device__ __forceinline__ uint32_t lane_ctrl_bytes(const uint8_t *in, uint64_t 
         uint32_t codes = 0;
 #pragma unroll
         for (uint32_t i = 0; i < P / 4; ++i) {
-            const uint32_t x = (i == 0) ? (base[i] & keep) : base[i];
+            const uint32_t x = (i == 0) ? (gptr(base)[i] & keep) : gptr(base)[i];
             codes += __builtin_popcount(x) + __builtin_popcount(x & 0xAAAAAAAAu);
         }
-        const uint32_t e = sh ? (base[P / 4] & ~keep) : 0u;
+        const uint32_t e = sh ? (gptr(base)[P / 4] & ~keep) : 0u;
         codes += __builtin_popcount(e) + __builtin_popcount(e & 0xAAAAAAAAu);
         return 4u * P + codes;
     }
@@ -340,16 +340,16 @@ __device__ __forceinline__ void load_segment_values(const EncodeStream &e, uint6
         uint32_t x[4] = {0u, 0u, 0u, 0u};
         uint32_t r = 4, pv = 0;
         if (full) {
-            const u32x4 w = *(const u32x4 *)src;
+            const u32x4 w = *gptr((const u32x4 *)src);
             x[0] = w.x; x[1] = w.y; x[2] = w.z; x[3] = w.w;
-            if (DELTA) pv = b ? src[-1] : e.start;
+            if (DELTA) pv = b ? gptr(src)[-1] : e.start;
         } else {
             const uint64_t i0 = 4 * b;
             r = i0 < e.n ? (uint32_t)((e.n - i0) < 4 ? (e.n - i0) : 4) : 0u;
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j)
-                if (j < r) x[j] = src[j];
-            if (DELTA && r) pv = b ? src[-1] : e.start;
+                if (j < r) x[j] = gptr(src)[j];
+            if (DELTA && r) pv = b ? gptr(src)[-1] : e.start;
         }
         uint32_t ctrl = 0, bytes = 0;
 #pragma unroll
@@ -393,7 +393,7 @@ __device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         const uint64_t b = s * kSegCtrl + kWave * k + lane;
-        if (b < nblocks) e.out[b] = (uint8_t)sv.c[k];
+        if (b < nblocks) gptr(e.out)[b] = (uint8_t)sv.c[k];
     }
     uint8_t *dst = e.out + nblocks + boff;
     const uint32_t sh = (uint32_t)((uintptr_t)dst & 15u);
@@ -433,11 +433,11 @@ __device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64
         if (c < nch) {
             const uint32_t lo = 16 * c, hi = lo + 16;
             if (lo >= sh && hi <= end) {
-                *(u32x4a *)(abase + lo) = ((const u32x4a *)stage)[c];
+                *gptr((u32x4a *)(abase + lo)) = ((const u32x4a *)stage)[c];
             } else {
                 const uint32_t from = lo > sh ? lo : sh;
                 const uint32_t to = hi < end ? hi : end;
-                for (uint32_t q = from; q < to; ++q) abase[q] = (uint8_t)(stage[q >> 2] >> (8u * (q & 3u)));
+                for (uint32_t q = from; q < to; ++q) gptr(abase)[q] = (uint8_t)(stage[q >> 2] >> (8u * (q & 3u)));
             }
         }
     }
