@@ -45,10 +45,21 @@ __device__ __forceinline__ SegCtrl load_seg_ctrl(const DecodeArgs &p, uint64_t s
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) r.c[k] = gptr(cp)[kWave * k];
     } else {
+        // all four loads are issued before any is used (a block past the end
+        // reads the last control byte instead, and is masked to no codes), so
+        // a short segment costs one round trip to memory, not four
+        const uint64_t nblocks = (p.n + 3) >> 2;
+        const uint64_t b0 = s * kSegCtrl + lane;
+        uint32_t raw[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint64_t b = b0 + kWave * k;
+            raw[k] = gptr(p.in)[b < nblocks ? b : nblocks - 1];
+        }
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
             const uint32_t m = block_ints(p, s, k, lane);
-            r.c[k] = m ? (gptr(cp)[kWave * k] & ((1u << (2 * m)) - 1u)) : 0u;
+            r.c[k] = m ? (raw[k] & ((1u << (2 * m)) - 1u)) : 0u;
         }
     }
     return r;
