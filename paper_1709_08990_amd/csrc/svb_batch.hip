@@ -57,41 +57,31 @@ __global__ __launch_bounds__(kThreads) void batch_count_kernel(BatchArgs a) {
     a.litems[i] = segs;
 }
 
-__device__ __forceinline__ void map_task(const BatchArgs &a, uint32_t t, uint32_t i, uint32_t b, uint32_t e) {
-    a.item_list[t] = i | (t + 1 == e ? kLastBit : 0u);
-    a.item_first[t] = b;
-}
-
-// Task -> list.  A thread maps the tasks of its own list when there are at
-// most 64 of them; the lanes of the wave share the longer lists.
+// Task -> list: thread t finds the list i with lbase[i] <= t < lbase[i + 1]
+// (a binary search over the list bases), so the mapping costs the same
+// however the tasks are spread over the lists.  If the tasks overflow the
+// caller's integer bound, nothing is done: decode reports
+// SVB_BATCH_OVERFLOW, encode marks every list's size.
 __global__ __launch_bounds__(kThreads) void batch_map_kernel(BatchArgs a) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool overflow = a.lbase[a.m] > a.t_cap;
-    const bool mine = i < a.m;
-    if (overflow) {
-        // the caller's integer bound was too small: nothing is done
-        if (i == 0 && a.err) *a.err = SVB_BATCH_OVERFLOW;
-        if (mine && a.out_bytes) a.out_bytes[i] = ~0ull;
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t total = a.lbase[a.m];
+    if (total > a.t_cap) {
+        if (t == 0 && a.err) *a.err = SVB_BATCH_OVERFLOW;
+        if (t < a.m && a.out_bytes) a.out_bytes[t] = ~0ull;
         return;
     }
-    uint32_t b = 0, e = 0;
-    if (mine) {
-        b = a.lbase[i];
-        e = b + a.litems[i];
+    if (t >= total) return;
+    uint32_t lo = 0, hi = a.m;  // invariant: lbase[lo] <= t < lbase[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.lbase[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
     }
-    const bool longer = e - b > (uint32_t)kWave;
-    if (mine && !longer)
-        for (uint32_t t = b; t < e; ++t) map_task(a, t, (uint32_t)i, b, e);
-    uint64_t todo = __ballot(mine && longer);
-    while (todo) {
-        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
-        todo &= todo - 1;
-        const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, l);
-        const uint32_t el = (uint32_t)__builtin_amdgcn_readlane((int)e, l);
-        const uint32_t il = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, l);
-        for (uint32_t t = bl + lane; t < el; t += kWave) map_task(a, t, il, bl, el);
-    }
+    const uint32_t e = a.lbase[lo + 1];
+    a.item_list[t] = lo | ((uint32_t)t + 1 == e ? kLastBit : 0u);
+    a.item_first[t] = a.lbase[lo];
 }
 
 // Total tasks, or 0 if they overflow the scratch.
@@ -419,7 +409,8 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
                 hipLaunchKernelGGL((batch_count_kernel<false>), dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
             break;
         case kBatchMap:
-            hipLaunchKernelGGL(batch_map_kernel, dim3(list_grid(a.m)), dim3(kThreads), 0, s, a);
+            // one thread per task (t_cap >= m, so the overflow path also reaches every list)
+            hipLaunchKernelGGL(batch_map_kernel, dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
             break;
         case kBatchDesc:
             if (encode)
