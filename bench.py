@@ -415,8 +415,9 @@ def latency_summary(lat, ints, wall):
 def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
                     arena_bytes=1 << 30, slots=4, max_batch_lists=8192):
     """Serving loop over a device-resident pool of delta-coded posting lists: closed-loop saturation,
-    then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate, each query 2..8 lists
-    chosen uniformly; latency from arrival to the host seeing the batch complete."""
+    then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate, then the highest probed
+    Poisson rate an open loop sustains and 0.5x / 0.8x of that; each query 2..8 lists chosen
+    uniformly; latency from arrival to the host seeing the batch complete."""
     from paper_1709_08990_amd import serve
     t0 = time.perf_counter()
     pool = build_pool(svb, torch, np, inputs, lists, total, cap, seed=91)
@@ -479,6 +480,34 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
         opened.append(r)
         log("serving open loop %.1fx: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
             % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+    # what an open loop sustains: the highest probed Poisson rate that keeps up (p50 under 1 ms)
+    sustained = 0.0
+    for frac in (0.2, 0.3, 0.4, 0.5, 0.6):
+        rate = frac * sat["qps"]
+        times, qo, ids = inputs.poisson_queries_flat(int(rate * (1.0 + warmup)), rate, lists, seed=131 + int(100 * frac))
+        lat, wall = server.replay((qo, ids), arrivals=times)
+        keep = times >= warmup
+        ok = np.percentile(lat[keep], 50) < 1e-3 and lat.size / wall > 0.95 * rate
+        log("serving open-loop probe %.2fx: %s" % (frac, "keeps up" if ok else "falls behind"))
+        if not ok:
+            break
+        sustained = rate
+    at_sustained = []
+    for load in (0.5, 0.8):
+        rate = load * sustained
+        if rate <= 0:
+            continue
+        nq = max(1000, int(rate * (seconds + warmup)))
+        times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=151 + int(10 * load))
+        lat, wall = server.replay((qo, ids), arrivals=times)
+        keep = times >= warmup
+        ints = query_ints(qo, ids)
+        r = latency_summary(lat[keep], ints[keep].sum(), wall - warmup)
+        r.update({"load_of_sustained": load, "offered_qps": rate, "window_s": float(times[-1] - warmup),
+                  "warmup_s": warmup})
+        at_sustained.append(r)
+        log("serving open loop %.1fx of sustained: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
+            % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
     st = server.stats()
     server.close()
     assert st["err"] == 0, "a served batch reported corrupt input"
@@ -486,7 +515,8 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
                      "max_list": int(h_counts.max()), "median_list": float(np.median(h_counts))},
             "arena_bytes": arena_bytes, "slots": slots, "max_batch_lists": max_batch_lists,
             "results_checked": len(check), "closed_loop": closed, "saturation_qps": sat["qps"],
-            "saturation_uint32_per_s": sat["uint32_per_s"], "open_loop": opened, "server_stats": st}
+            "saturation_uint32_per_s": sat["uint32_per_s"], "open_loop": opened,
+            "open_loop_sustained_qps": sustained, "open_loop_at_sustained": at_sustained, "server_stats": st}
 
 
 def run_cpu_baseline(x, min_seconds=10.0):

@@ -241,6 +241,12 @@ int svb_server_poll(void *server, uint64_t *ids, uint64_t *arena_off, uint64_t *
 int svb_server_release(void *server, uint64_t query_id);
 uint32_t *svb_server_arena(void *server);
 int svb_server_stats(void *server, uint64_t *out, uint32_t cap);
+/* Batching policy of svb_server_step: while a batch is on the device, the
+ * next one is launched only once min_lists lists are admitted or its oldest
+ * query has waited max_wait_us microseconds (with nothing on the device it
+ * leaves at once).  Defaults 1024 lists, 20 us; (0, 0) launches whenever a
+ * slot is free.  Larger batches cost the host less per query. */
+int svb_server_set_batching(void *server, uint32_t min_lists, uint32_t max_wait_us);
 int svb_server_destroy(void *server);
 
 /*

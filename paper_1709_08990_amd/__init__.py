@@ -18,6 +18,7 @@ __all__ = [
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
     "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
+    "svb_server_set_batching",
     "encode", "decode",
     "LIB_PATH",
 ]
@@ -65,6 +66,7 @@ def lib():
             "svb_server_stats": (i32, [vp, vp, u32]),
             "svb_server_destroy": (i32, [vp]),
             "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, vp, vp]),
+            "svb_server_set_batching": (i32, [vp, u32, u32]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -275,6 +277,10 @@ def svb_server_stats(server):
     out = np.zeros(len(SERVER_STATS), dtype=np.uint64)
     _check(lib().svb_server_stats(server, out.ctypes.data, len(SERVER_STATS)), "svb_server_stats")
     return {k: int(v) for k, v in zip(SERVER_STATS, out)}
+
+
+def svb_server_set_batching(server, min_lists, max_wait_us):
+    return _check(lib().svb_server_set_batching(server, int(min_lists), int(max_wait_us)), "svb_server_set_batching")
 
 
 def svb_server_destroy(server):

@@ -52,6 +52,7 @@ struct Query {
     std::vector<uint64_t> big_counts;
     uint32_t list(uint32_t i) const { return k <= kInlineLists ? small_lists[i] : big_lists[i]; }
     uint64_t count(uint32_t i) const { return k <= kInlineLists ? small_counts[i] : big_counts[i]; }
+    uint64_t admit_ns;   // when it was admitted (steady clock)
     uint64_t ints;       // output integers
     uint64_t tasks;      // segments to decode
     uint64_t arena_off;  // in integers
@@ -110,6 +111,12 @@ struct Server {
     std::deque<uint32_t> completed_replay;         // complete (replay driver)
     std::vector<Slot> slots;
     uint32_t max_batch_lists = 0;
+    // Batching policy: with a batch on the device, the next one waits until
+    // min_batch_lists lists are admitted or its oldest query has waited
+    // max_wait_ns; with none on the device it leaves at once.
+    uint32_t min_batch_lists = 1024;
+    uint64_t max_wait_ns = 20000;
+    uint64_t admitted_lists = 0;
     uint64_t stats[8] = {};  // batches, lists, integers, queries admitted, queries completed, peak slots busy,
                              // corrupt batches, arena peak integers in use
     uint64_t in_use = 0;
@@ -210,8 +217,16 @@ int retire(Server &s, bool block) {
 // Admits waiting queries in arrival order.  Consecutive queries are carved
 // out of one free range one after the other, so the free-range map changes
 // once per range, not once per query.
+uint64_t steady_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 void admit(Server &s) {
     if (s.admit_blocked) return;  // the arena has not changed since the front query failed to fit
+    if (s.waiting.empty()) return;
+    const uint64_t now = steady_ns();
     while (!s.waiting.empty()) {
         auto it = s.free_ranges.end();
         if (s.slab[s.waiting.front()].ints) {
@@ -232,6 +247,8 @@ void admit(Server &s) {
             q.arena_off = q.ints ? pos : 0;
             pos += q.ints;
             q.state = 1;
+            q.admit_ns = now;
+            s.admitted_lists += q.k;
             s.admitted.push_back(e);
             s.waiting.pop_front();
             s.stats[3]++;
@@ -251,12 +268,16 @@ void admit(Server &s) {
 int launch(Server &s) {
     if (s.admitted.empty()) return SVB_OK;
     Slot *slot = nullptr;
-    for (Slot &sl : s.slots)
-        if (!sl.busy) {
-            slot = &sl;
-            break;
-        }
+    bool busy = false;
+    for (Slot &sl : s.slots) {
+        if (!sl.busy && !slot) slot = &sl;
+        busy |= sl.busy;
+    }
     if (!slot) return SVB_OK;
+    // with work on the device, let a small batch grow for a while
+    if (busy && s.admitted_lists < s.min_batch_lists &&
+        steady_ns() - s.slab[s.admitted.front()].admit_ns < s.max_wait_ns)
+        return SVB_OK;
     // take admitted queries in order while their lists fit the batch limit
     size_t take = 0;
     uint32_t lists = 0;
@@ -269,6 +290,7 @@ int launch(Server &s) {
         tasks += q.tasks;
         ++take;
     }
+    s.admitted_lists -= lists;
     int st = ensure_slot_capacity(*slot, lists, tasks);
     if (st != SVB_OK) return st;
     const uint32_t cap = lists;  // the table is laid out for exactly this batch
@@ -322,9 +344,9 @@ int launch(Server &s) {
     s.stats[0]++;
     s.stats[1] += j;
     s.stats[2] += total;
-    uint64_t busy = 0;
-    for (Slot &sl : s.slots) busy += sl.busy ? 1 : 0;
-    s.stats[5] = std::max(s.stats[5], busy);
+    uint64_t nbusy = 0;
+    for (Slot &sl : s.slots) nbusy += sl.busy ? 1 : 0;
+    s.stats[5] = std::max(s.stats[5], nbusy);
     return SVB_OK;
 }
 
@@ -545,9 +567,14 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
     uint64_t next = 0, done = 0;
     int st = SVB_OK;
     while (done < nq) {
-        // arrivals that are due (open loop) or room under the outstanding limit (closed loop)
+        // arrivals that are due (open loop) or room under the outstanding limit (closed loop).
+        // A backlog beyond two batches' worth of waiting lists stays in the trace: the
+        // queries' latencies still count from their arrival times, and the server's
+        // working set does not grow with the backlog.
         const double t = now_s();
-        while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding)) {
+        const size_t backlog_cap = 2 * (size_t)s->max_batch_lists;
+        while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding) &&
+               s->waiting.size() < backlog_cap) {
             sent[next] = arrival_s ? arrival_s[next] : t;
             // the query's id is its index in the trace (replayed queries are not pollable)
             st = submit_locked(*s, next, (uint32_t)(qoff[next + 1] - qoff[next]), lists + qoff[next], false, nullptr);
@@ -588,6 +615,15 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
         }
     }
     if (wall_s) *wall_s = now_s();
+    return SVB_OK;
+}
+
+int svb_server_set_batching(void *server, uint32_t min_lists, uint32_t max_wait_us) {
+    Server *s = (Server *)server;
+    if (!s) return SVB_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->min_batch_lists = min_lists;
+    s->max_wait_ns = (uint64_t)max_wait_us * 1000;
     return SVB_OK;
 }
 

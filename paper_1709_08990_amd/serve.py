@@ -10,7 +10,7 @@ import time
 import numpy as np
 
 from . import (svb_server_create, svb_server_destroy, svb_server_poll, svb_server_release, svb_server_replay,
-               svb_server_stats, svb_server_step, svb_server_submit)
+               svb_server_set_batching, svb_server_stats, svb_server_step, svb_server_submit)
 
 
 class Server:
@@ -41,6 +41,11 @@ class Server:
 
     def stats(self):
         return svb_server_stats(self.handle)
+
+    def set_batching(self, min_lists, max_wait_us):
+        """While a batch is on the device, hold the next one until min_lists lists are admitted
+        or its oldest query has waited max_wait_us."""
+        svb_server_set_batching(self.handle, min_lists, max_wait_us)
 
     def replay(self, picks, arrivals=None, outstanding=0):
         """Native load generator: open loop at ``arrivals`` or closed loop with ``outstanding``
