@@ -294,8 +294,8 @@ int prepare_batch(const BatchCall &c, uint32_t C, uint64_t T, uint8_t *sc, Batch
              return launch_scan(a.litems, a.lbase, M, false, 0u, s, a.lbase + M, scan_scr);
          }))) != SVB_OK)
         return st;
-    if ((st = run("batch_map", kBatchMap)) != SVB_OK) return st;
-    if ((st = run("batch_task_bytes", kBatchItemBytes)) != SVB_OK) return st;
+    if (c.encode && (st = run("batch_map", kBatchMap)) != SVB_OK) return st;
+    if ((st = run(c.encode ? "batch_task_bytes" : "batch_map_bytes", kBatchItemBytes)) != SVB_OK) return st;
     if ((st = hip_status(timed("batch_scan_offsets", s, [&] {
              return launch_scan(a.ibytes, a.ioff, T, true, 0u, s, nullptr, scan_scr);
          }))) != SVB_OK)

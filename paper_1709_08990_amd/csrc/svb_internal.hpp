@@ -100,7 +100,7 @@ struct BatchArgs {
 };
 enum BatchPhase {
     kBatchCount = 0,
-    kBatchMap = 1,
+    kBatchMap = 1,      // encoding (decoding maps tasks in its byte counts)
     kBatchItemBytes = 2,
     kBatchItemSums = 3,
     kBatchWork = 4,

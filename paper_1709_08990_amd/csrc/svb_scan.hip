@@ -8,9 +8,11 @@
 // (64-bit, or 32-bit plus start modulo 2^32).
 //
 // Up to kSingleMax (16384) values: one workgroup of 1024 threads.  Above
-// that: reduce-then-scan over tiles of 16384 values (tile sums, one-workgroup
-// scan of the tile sums, per-tile scan with carry); one workgroup walking a
-// longer array step by step was measured slower than the three launches.
+// that: reduce-then-scan over tiles of 4096 values, one 256-thread workgroup
+// each (tile sums, one-workgroup scan of the tile sums, per-tile scan with
+// carry), so that a few hundred thousand values already spread over most of
+// the chip; one workgroup walking a longer array step by step was measured
+// slower than the three launches.
 #include <type_traits>
 
 #include "svb_device.hpp"
@@ -20,11 +22,12 @@ namespace svb {
 
 namespace {
 
-constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanThreads = 1024;                 // the single-workgroup scan
 constexpr uint32_t kScanPer = 16;
 constexpr uint32_t kScanTile = kScanThreads * kScanPer;  // values per workgroup step
-constexpr uint32_t kScanWaves = kScanThreads / kWave;
 constexpr uint64_t kSingleMax = kScanTile;
+constexpr uint32_t kTileThreads = 256;                   // the multi-workgroup scan
+constexpr uint32_t kTileVals = kTileThreads * kScanPer;
 
 template <bool WIDE>
 using acc_t = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
@@ -41,7 +44,7 @@ __device__ __forceinline__ uint64_t wave_scan_acc(uint64_t x) {
     return x;
 }
 
-// Loads the 16 values of thread `tid` in [base, base + kScanTile), 0 past m.
+// Loads the 16 values of thread `tid` from base on, 0 past m.
 __device__ __forceinline__ void load16(const uint32_t *in, uint64_t base, uint64_t m, uint32_t tid,
                                        uint32_t (&x)[kScanPer]) {
     const uint64_t i0 = base + (uint64_t)tid * kScanPer;
@@ -57,9 +60,10 @@ __device__ __forceinline__ void load16(const uint32_t *in, uint64_t base, uint64
     }
 }
 
-// Workgroup-wide exclusive prefix of each thread's 16-value sum; returns the
-// thread's prefix and writes the workgroup total to *total (all threads).
-template <typename A>
+// Workgroup-wide exclusive prefix of each thread's value over a workgroup of
+// W waves; returns the thread's prefix and writes the workgroup total to
+// *total (all threads).  s_wtot holds W + 1 entries.
+template <uint32_t W, typename A>
 __device__ __forceinline__ A block_prefix(A sum, A *s_wtot, A *total) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -68,14 +72,14 @@ __device__ __forceinline__ A block_prefix(A sum, A *s_wtot, A *total) {
     if (lane == kWave - 1) s_wtot[wave] = incl;
     __syncthreads();
     if (wave == 0) {
-        const A t = lane < kScanWaves ? s_wtot[lane] : (A)0;
+        const A t = lane < W ? s_wtot[lane] : (A)0;
         const A ti = wave_scan_acc(t);
-        if (lane < kScanWaves) s_wtot[lane] = ti - t;
-        if (lane == kWave - 1) s_wtot[kScanWaves] = ti;
+        if (lane < W) s_wtot[lane] = ti - t;
+        if (lane == kWave - 1) s_wtot[W] = ti;
     }
     __syncthreads();
     const A pre = s_wtot[wave] + incl - sum;
-    *total = s_wtot[kScanWaves];
+    *total = s_wtot[W];
     __syncthreads();
     return pre;
 }
@@ -130,7 +134,8 @@ template <bool WIDE>
 __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_t *in, void *out, uint64_t m,
                                                                    uint32_t start, void *total) {
     typedef acc_t<WIDE> A;
-    __shared__ A s_wtot[kScanWaves + 1];
+    constexpr uint32_t W = kScanThreads / kWave;
+    __shared__ A s_wtot[W + 1];
     const uint32_t tid = threadIdx.x;
     A carry = WIDE ? (A)0 : (A)start;
     for (uint64_t base = 0; base < m; base += kScanTile) {
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_
 #pragma unroll
         for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
         A step_total;
-        const A pre = block_prefix<A>(sum, s_wtot, &step_total);
+        const A pre = block_prefix<W, A>(sum, s_wtot, &step_total);
         store16<WIDE>(out, base, m, tid, carry + pre, x);
         carry += step_total;
     }
@@ -149,17 +154,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_
 
 // Tile t's sum into sums[t] (64-bit for WIDE).
 template <bool WIDE>
-__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t *in, uint64_t m, uint32_t *sums) {
+__global__ __launch_bounds__(kTileThreads) void scan_tile_sums_kernel(const uint32_t *in, uint64_t m, uint32_t *sums) {
     typedef acc_t<WIDE> A;
-    __shared__ A s_wtot[kScanWaves + 1];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    constexpr uint32_t W = kTileThreads / kWave;
+    __shared__ A s_wtot[W + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kTileVals;
     uint32_t x[kScanPer];
     load16(in, base, m, threadIdx.x, x);
     A sum = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
     A tot;
-    (void)block_prefix<A>(sum, s_wtot, &tot);
+    (void)block_prefix<W, A>(sum, s_wtot, &tot);
     if (threadIdx.x == 0) {
         if (WIDE) {
             // split into two 32-bit words so the tile sums scan as u32 pairs below
@@ -176,7 +182,8 @@ template <bool WIDE>
 __global__ __launch_bounds__(kScanThreads) void scan_tile_prefix_kernel(const uint32_t *sums, uint64_t tiles,
                                                                         uint64_t *pre, uint32_t start, void *total) {
     typedef acc_t<WIDE> A;
-    __shared__ A s_wtot[kScanWaves + 1];
+    constexpr uint32_t W = kScanThreads / kWave;
+    __shared__ A s_wtot[W + 1];
     const uint32_t tid = threadIdx.x;
     A carry = WIDE ? (A)0 : (A)start;
     for (uint64_t base = 0; base < tiles; base += kScanThreads) {
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_prefix_kernel(const ui
         A v = 0;
         if (t < tiles) v = WIDE ? (A)(sums[2 * t] | ((uint64_t)sums[2 * t + 1] << 32)) : (A)sums[t];
         A step_total;
-        const A p = block_prefix<A>(v, s_wtot, &step_total);
+        const A p = block_prefix<W, A>(v, s_wtot, &step_total);
         if (t < tiles) pre[t] = (uint64_t)(carry + p);
         carry += step_total;
     }
@@ -193,18 +200,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_prefix_kernel(const ui
 
 // Per-tile scan with the tile's carry.
 template <bool WIDE>
-__global__ __launch_bounds__(kScanThreads) void scan_tile_final_kernel(const uint32_t *in, void *out, uint64_t m,
+__global__ __launch_bounds__(kTileThreads) void scan_tile_final_kernel(const uint32_t *in, void *out, uint64_t m,
                                                                        const uint64_t *pre) {
     typedef acc_t<WIDE> A;
-    __shared__ A s_wtot[kScanWaves + 1];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    constexpr uint32_t W = kTileThreads / kWave;
+    __shared__ A s_wtot[W + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * kTileVals;
     uint32_t x[kScanPer];
     load16(in, base, m, threadIdx.x, x);
     A sum = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
     A tot;
-    const A p = block_prefix<A>(sum, s_wtot, &tot);
+    const A p = block_prefix<W, A>(sum, s_wtot, &tot);
     store16<WIDE>(out, base, m, threadIdx.x, (A)pre[blockIdx.x] + p, x);
 }
 
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_final_kernel(const uin
 
 uint64_t scan_scratch_bytes(uint64_t m) {
     if (m <= kSingleMax) return 0;
-    const uint64_t tiles = (m + kScanTile - 1) / kScanTile;
+    const uint64_t tiles = (m + kTileVals - 1) / kTileVals;
     return 8 * tiles + 8 * tiles;  // tile sums (two words each when wide), tile prefixes
 }
 
@@ -226,20 +234,20 @@ hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uin
         return hipGetLastError();
     }
     if (!scratch) return hipErrorInvalidValue;
-    const uint64_t tiles = (m + kScanTile - 1) / kScanTile;
+    const uint64_t tiles = (m + kTileVals - 1) / kTileVals;
     uint32_t *sums = (uint32_t *)scratch;
     uint64_t *pre = (uint64_t *)((uint8_t *)scratch + 8 * tiles);
     if (wide) {
-        hipLaunchKernelGGL((scan_tile_sums_kernel<true>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, m, sums);
+        hipLaunchKernelGGL((scan_tile_sums_kernel<true>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, m, sums);
         hipLaunchKernelGGL((scan_tile_prefix_kernel<true>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
                            total);
-        hipLaunchKernelGGL((scan_tile_final_kernel<true>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, out, m,
+        hipLaunchKernelGGL((scan_tile_final_kernel<true>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, out, m,
                            pre);
     } else {
-        hipLaunchKernelGGL((scan_tile_sums_kernel<false>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, m, sums);
+        hipLaunchKernelGGL((scan_tile_sums_kernel<false>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, m, sums);
         hipLaunchKernelGGL((scan_tile_prefix_kernel<false>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
                            total);
-        hipLaunchKernelGGL((scan_tile_final_kernel<false>), dim3((uint32_t)tiles), dim3(kScanThreads), 0, s, in, out, m,
+        hipLaunchKernelGGL((scan_tile_final_kernel<false>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, out, m,
                            pre);
     }
     return hipGetLastError();

@@ -13,8 +13,8 @@ torch = pytest.importorskip("torch")
 svb = pytest.importorskip("paper_1709_08990_amd")
 
 CHUNKS = [1, 2, 4, 8, 16]
-EDGE_SIZES = [0, 1, 3, 4, 5, 63, 64, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
-              16385, 40000, 100003]
+EDGE_SIZES = [0, 1, 3, 4, 5, 63, 64, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4095,
+              4096, 4097, 8191, 8192, 8193, 16385, 40000, 100003]
 SENTINEL32 = 0x5EEDF00D
 SENTINEL8 = 0xA7
 
