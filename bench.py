@@ -22,7 +22,9 @@ Prints one JSON line.  Besides the headline it carries:
                 decode of 2^28 integers with unpredictable lengths;
   batched       200,000 delta-coded posting lists (about 3e8 integers):
                 autotuned batched decode and encode, against the single-array
-                rate and against one svb_delta_decode call per list;
+                rate, against one array of the same integers (the lists back
+                to back, one stream) and against one svb_delta_decode call
+                per list;
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
@@ -354,6 +356,21 @@ def measure_batched(svb, torch, np, inputs, steps, warmup, per_list=True):
            "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
            "kernels_ms": kms, "round_trip_ok": ok,
            "encode": {"ms_per_call": 1e3 * ewall / steps, "uint32_per_s": total / ewall * steps, "kernels_ms": ekms}}
+    # the same integers as one array: the lists back to back, delta-coded as a single stream (so the
+    # same byte lengths, bar one difference per list boundary), decoded by one svb_delta_decode call
+    one = torch.empty(svb.svb_max_compressed_bytes(total), dtype=torch.uint8, device="cuda")
+    one_size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(total, x_dev, one, 0, one_size)
+    torch.cuda.synchronize()
+    one_bytes = int(one_size.item())
+    out.zero_()
+    owall, okms = timed_steps(svb, torch, lambda: svb.svb_delta_decode(total, one, one_bytes, out, 0), steps, warmup)
+    one_ms = 1e3 * owall / steps
+    res["single_array_same_ints"] = {"ms_per_call": one_ms, "uint32_per_s": total / (one_ms * 1e-3),
+                                     "compressed_bytes": one_bytes, "kernels_ms": okms,
+                                     "round_trip_ok": bool(torch.equal(out, x_dev))}
+    res["vs_single_array_same_ints"] = res["uint32_per_s"] / res["single_array_same_ints"]["uint32_per_s"]
+    del one
     if not per_list:
         del x_dev, comp, out
         return res
@@ -661,8 +678,8 @@ def main():
             assert rb["one_call_per_list"]["round_trip_ok"], "per-list decode mismatch"
             rb["vs_one_call_per_list"] = rb["uint32_per_s"] / rb["one_call_per_list"]["uint32_per_s"]
         line["batched"] = rb
-        log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array)"
-            % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"]))
+        log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array; %.2fx one array of the same ints)"
+            % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"], rb["vs_single_array_same_ints"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)

@@ -6,7 +6,9 @@ code with the GPU library (``paper_1709_08990_amd``), and neither imports the
 other.  The C part is compiled with gcc into ``oracle/libsvbref.so``.
 
 Every function here follows the plain definition of the format (Section 3,
-Section 4 and Fig. 3 of the paper) and of differential coding (Section 2).
+Section 4 and Fig. 3 of the paper), of differential coding (Section 2), and of
+the two operations on compressed lists benchmarked in Section 5 (seek: the
+first position whose value reaches a target; select: the value at a position).
 """
 import ctypes
 import os
@@ -52,6 +54,12 @@ def lib():
         L.svbref_decode.restype = ctypes.c_int64
         L.svbref_encoded_size.argtypes = [u32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32]
         L.svbref_encoded_size.restype = ctypes.c_uint64
+        L.svbref_seek.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
+                                  ctypes.c_uint32, u32p]
+        L.svbref_seek.restype = ctypes.c_int64
+        L.svbref_select.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
+                                    ctypes.c_uint64, u32p]
+        L.svbref_select.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -111,6 +119,34 @@ def length_histogram():
     h = (ctypes.c_uint64 * 4)()
     lib().svbref_length_histogram(h)
     return [int(v) for v in h]
+
+
+# --- operations on the compressed stream (Section 5: seek and select) --------
+
+def seek(stream, n, target, delta=False, start=0):
+    """(position, value) of the first integer whose value is >= target, by walking the stream in
+    order; (n, 0) if there is none.  Raises ValueError on a stream too short for the walk."""
+    s, sp = _u8(stream)
+    v = np.zeros(1, dtype=np.uint32)
+    _, vp = _u32(v)
+    pos = lib().svbref_seek(sp, s.size, int(n), int(bool(delta)), int(start) & 0xFFFFFFFF,
+                            int(target) & 0xFFFFFFFF, vp)
+    if pos < 0:
+        raise ValueError("corrupt or truncated Stream VByte stream")
+    return int(pos), int(v[0])
+
+
+def select(stream, n, i, delta=False, start=0):
+    """Value of integer i (from 0), walking the stream up to it.  Raises IndexError if i >= n and
+    ValueError on a stream too short for the walk."""
+    if not 0 <= int(i) < int(n):
+        raise IndexError("select index past the end of the list")
+    s, sp = _u8(stream)
+    v = np.zeros(1, dtype=np.uint32)
+    _, vp = _u32(v)
+    if lib().svbref_select(sp, s.size, int(n), int(bool(delta)), int(start) & 0xFFFFFFFF, int(i), vp) != 0:
+        raise ValueError("corrupt or truncated Stream VByte stream")
+    return int(v[0])
 
 
 # --- batched: Stream VByte applied to each list on its own -------------------

@@ -85,3 +85,20 @@ def encoded_size(values, delta=False, start=0) -> int:
     """ceil(N/4) + sum of byte lengths (Section 3 and Section 4)."""
     vals = deltas(values, start) if delta else list(values)
     return (len(vals) + 3) // 4 + sum(byte_length(v) for v in vals)
+
+
+def seek(stream: bytes, n: int, target: int, delta=False, start=0):
+    """First position whose decoded value is >= target, with that value; (n, 0) if none
+    (Section 5's seek on a compressed stream, stated on the decoded values)."""
+    vals = decode(stream, n, delta, start)
+    for i, v in enumerate(vals):
+        if v >= target:
+            return i, v
+    return n, 0
+
+
+def select(stream: bytes, n: int, i: int, delta=False, start=0):
+    """Decoded value at position i (Section 5's select)."""
+    if not 0 <= i < n:
+        raise IndexError("select index past the end of the list")
+    return decode(stream, n, delta, start)[i]

@@ -129,3 +129,58 @@ uint64_t svbref_encoded_size(const uint32_t *x, uint64_t n, int delta, uint32_t 
     }
     return total;
 }
+
+/* Operations on the compressed stream itself (Section 5, the seek and select
+ * benchmark): both walk the stream one integer at a time, as the decoder
+ * above does, and stop at the answer.  A value is the running sum when
+ * delta != 0 and the stored integer otherwise.
+ *
+ * Seek: the position of the first integer whose value is >= target, its value
+ * in *value.  Returns n (and *value = 0) if none is, or -1 if the stream is
+ * shorter than its control stream or than the data read before the answer. */
+int64_t svbref_seek(const uint8_t *in, uint64_t in_bytes, uint64_t n, int delta, uint32_t start,
+                    uint32_t target, uint32_t *value)
+{
+    uint64_t ncontrol = (n + 3) / 4;
+    if (in_bytes < ncontrol) return -1;
+    uint64_t p = ncontrol;
+    uint32_t prev = start;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t len = ((in[i / 4] >> (2u * (uint32_t)(i % 4))) & 3u) + 1u;
+        if (p + len > in_bytes) return -1;
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < len; ++k) v |= (uint32_t)in[p + k] << (8u * k);
+        p += len;
+        if (delta) {
+            prev = prev + v;
+            v = prev;
+        }
+        if (v >= target) {
+            *value = v;
+            return (int64_t)i;
+        }
+    }
+    *value = 0;
+    return (int64_t)n;
+}
+
+/* Select: the value of integer i (counted from 0) in *value.  Returns 0, or
+ * -1 if i >= n or the stream is shorter than what is read up to integer i. */
+int svbref_select(const uint8_t *in, uint64_t in_bytes, uint64_t n, int delta, uint32_t start,
+                  uint64_t i, uint32_t *value)
+{
+    uint64_t ncontrol = (n + 3) / 4;
+    if (i >= n || in_bytes < ncontrol) return -1;
+    uint64_t p = ncontrol;
+    uint32_t prev = start;
+    for (uint64_t k = 0; k <= i; ++k) {
+        uint32_t len = ((in[k / 4] >> (2u * (uint32_t)(k % 4))) & 3u) + 1u;
+        if (p + len > in_bytes) return -1;
+        uint32_t v = 0;
+        for (uint32_t b = 0; b < len; ++b) v |= (uint32_t)in[p + b] << (8u * b);
+        p += len;
+        prev = delta ? prev + v : v;
+    }
+    *value = prev;
+    return 0;
+}

@@ -153,6 +153,33 @@ def posting_lists(m=200_000, total=300_000_000, cap=1 << 20, seed=4):
     return sorted_sets(lens, seed=seed + 1)
 
 
+def seek_lists(m, bits, n=256, seed=9):
+    """Seek/select workload (Section 5's experiment, scaled to m lists): per list, n deltas drawn
+    uniformly from [0, 2^bits), bits <= 24, and their running sum as the list (non-decreasing, equal
+    neighbours wherever a delta is 0).  Returns (values uint32[m * n], offsets int64[m + 1])."""
+    if not 1 <= bits <= 24:
+        raise ValueError("bits must be in 1..24")
+    rng = np.random.default_rng(seed)
+    d = rng.integers(0, 1 << bits, size=(m, n), dtype=np.uint64)
+    vals = np.cumsum(d, axis=1, dtype=np.uint64).astype(np.uint32).reshape(-1)
+    return vals, np.arange(m + 1, dtype=np.int64) * n
+
+
+def seek_queries(values, offsets, q, seed=10):
+    """q queries over the lists of (values, offsets): a uniform list id, a target uniform in
+    [0, last value + 2) of that list (so some targets lie past every value), and a uniform index
+    below the list's length.  Empty lists get index 0.  Returns (list ids uint32, targets uint32,
+    indexes uint64)."""
+    rng = np.random.default_rng(seed)
+    m = offsets.size - 1
+    ids = rng.integers(0, m, size=q).astype(np.int64)
+    lens = (offsets[ids + 1] - offsets[ids]).astype(np.int64)
+    last = np.where(lens > 0, values[np.maximum(offsets[ids + 1] - 1, 0)].astype(np.int64), 0)
+    targets = np.minimum((rng.random(q) * (last + 2)).astype(np.int64), 0xFFFFFFFF).astype(np.uint32)
+    idx = np.where(lens > 0, (rng.random(q) * lens).astype(np.int64), 0).astype(np.uint64)
+    return ids.astype(np.uint32), targets, idx
+
+
 def poisson_queries(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8):
     """Arrival times (seconds, Poisson process at ``qps``) and, per query, kmin..kmax distinct
     list ids chosen uniformly.  Returns (times float64[n], list of int64 arrays)."""

@@ -268,3 +268,93 @@ def test_random_stream_fuzz(n):
 def test_truncated_control_stream_is_corrupt():
     with pytest.raises(ValueError):
         oracle.decode(np.zeros(1, dtype=np.uint8), 5)
+
+
+# ---------------------------------------------------------------- seek and select (Section 5)
+
+def _first_at_least(values, target):
+    """Brute force: the first position whose value is >= target, or len(values)."""
+    for i, v in enumerate(values):
+        if int(v) >= target:
+            return i
+    return len(values)
+
+
+def test_seek_select_prefix_sum_example():
+    """Section 2's running-sum example, (3, 4, 12, 1) -> (3, 7, 19, 20), stored as differences:
+    seek and select answer on the running sums, not on the stored differences."""
+    x = np.array([3, 7, 19, 20], dtype=np.uint32)
+    s = oracle.encode(x, delta=True)
+    assert oracle.select(s, 4, 2, delta=True) == 19
+    assert oracle.seek(s, 4, 8, delta=True) == (2, 19)
+    assert oracle.seek(s, 4, 19, delta=True) == (2, 19)
+    assert oracle.seek(s, 4, 0, delta=True) == (0, 3)
+    assert oracle.seek(s, 4, 21, delta=True) == (4, 0)
+    with pytest.raises(IndexError):
+        oracle.select(s, 4, 4, delta=True)
+
+
+@pytest.mark.parametrize("bits", [1, 7, 8, 9, 16, 24])
+def test_seek_on_sorted_lists_is_lower_bound(bits):
+    """The paper's seek workload (Section 5: 256 deltas in [0, 2^b), b <= 24, prefix-summed): on a
+    non-decreasing list, seek is the textbook lower bound (numpy's searchsorted, side='left'), and
+    select(i) is the i-th input value."""
+    vals, offs = inputs.seek_lists(8, bits, seed=100 + bits)
+    rng = np.random.default_rng(bits)
+    for li in range(8):
+        x = vals[offs[li]:offs[li + 1]]
+        assert np.all(np.diff(x.astype(np.int64)) >= 0)
+        s = oracle.encode(x, delta=True)
+        for t in list(rng.integers(0, int(x[-1]) + 2, size=40)) + [0, int(x[0]), int(x[-1]), int(x[-1]) + 1]:
+            pos, val = oracle.seek(s, x.size, int(t), delta=True)
+            assert pos == int(np.searchsorted(x, t, side="left"))
+            assert val == (int(x[pos]) if pos < x.size else 0)
+        for i in list(rng.integers(0, x.size, size=40)) + [0, x.size - 1]:
+            assert oracle.select(s, x.size, int(i), delta=True) == int(x[i])
+
+
+@pytest.mark.parametrize("delta", [False, True])
+def test_seek_select_brute_force_unsorted(delta):
+    """Unsorted lists (plain coding, or differences that wrap modulo 2^32): seek is still the
+    first position at or above the target, found by brute force on the input values; the
+    pure-Python oracle, which works on a full decode, agrees with the C walk."""
+    rng = np.random.default_rng(7 + delta)
+    for n in [0, 1, 2, 3, 4, 5, 9, 33]:
+        x = (rng.integers(0, 1 << 32, size=n, dtype=np.uint64) >> rng.integers(0, 32, size=n).astype(np.uint64)
+             ).astype(np.uint32)
+        start = int(rng.integers(0, 1 << 32))
+        s = oracle.encode(x, delta=delta, start=start)
+        py = bytes(ref.encode([int(v) for v in x], delta=delta, start=start))
+        assert py == s.tobytes()
+        targets = sorted({0, 1, MASK32} | {int(v) for v in x} | {int(v) + 1 & MASK32 for v in x})
+        for t in targets:
+            want = _first_at_least(x, t)
+            got = oracle.seek(s, n, t, delta=delta, start=start)
+            assert got == (want, int(x[want]) if want < n else 0)
+            assert ref.seek(py, n, t, delta=delta, start=start) == got
+        for i in range(n):
+            assert oracle.select(s, n, i, delta=delta, start=start) == int(x[i])
+            assert ref.select(py, n, i, delta=delta, start=start) == int(x[i])
+
+
+def test_seek_select_invariants():
+    """For any list and target: seek returns a position whose value reaches the target and no
+    earlier value does; seek of a list's own value x_i lands at or before i."""
+    rng = np.random.default_rng(11)
+    x = rng.integers(0, 1000, size=500).astype(np.uint32)
+    s = oracle.encode(x)
+    for i in range(0, 500, 7):
+        pos, val = oracle.seek(s, 500, int(x[i]))
+        assert pos <= i and val == int(x[pos]) >= int(x[i])
+        assert np.all(x[:pos] < x[i])
+    assert oracle.seek(s, 500, 1000) == (500, 0)
+
+
+def test_seek_truncated_stream_is_corrupt():
+    """A stream shorter than the data read before the answer is refused (Section 4's layout)."""
+    x = np.arange(1, 100, dtype=np.uint32) * 1000
+    s = oracle.encode(x, delta=True)
+    with pytest.raises(ValueError):
+        oracle.seek(s[:-5], x.size, int(x[-1]), delta=True)
+    with pytest.raises(ValueError):
+        oracle.select(s[:-5], x.size, x.size - 1, delta=True)
