@@ -68,6 +68,10 @@ enum svb_status {
  * than the caller's total_ints bound (nothing is decoded then). */
 #define SVB_BATCH_OVERFLOW 3u
 
+/* Value a seek or select call writes to `err` when a query names a list past
+ * the index's last one, or selects a position past its list's end. */
+#define SVB_QUERY_OUT_OF_RANGE 4u
+
 /* Largest n accepted by the single-stream calls (2^40 integers). */
 #define SVB_MAX_N (((uint64_t)1) << 40)
 
@@ -267,6 +271,43 @@ int svb_server_destroy(void *server);
  */
 int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
                       uint32_t outstanding, double *latency_s, double *wall_s);
+
+/*
+ * Seek and select on resident compressed lists (Section 5 benchmarks both
+ * operations on the compressed stream).  For list L, value x_i is its i-th
+ * integer after the running sum from starts[L] when the lists are
+ * delta-coded (Section 2), else the stored integer.
+ *   seek(L, target)  the first position i with x_i >= target, and x_i; the
+ *                    list's length and 0 if no value reaches the target;
+ *   select(L, i)     x_i.
+ * Both are exact for any list, sorted or not.
+ *
+ * svb_seek_index_create builds a skip index over m lists laid out as for
+ * svb_server_create (device arrays counts, in_off, in_bytes, starts or NULL;
+ * streams in `in`, which must stay valid and unchanged while the index
+ * lives; total_ints bounds sum(counts)).  Per 1024-integer segment of each
+ * list the index keeps the segment's byte offset, the running sum before it
+ * and the running maximum of the list's values up to its end (68 bytes per
+ * segment, 4 per list).  It synchronises `stream`.  Returns SVB_ERR_INVALID
+ * if a list is corrupt (data shorter than its control bytes describe) or the
+ * counts exceed total_ints.
+ *
+ * svb_seek_batch answers q seeks: list[k] and target[k] (device arrays) give
+ * pos[k] (uint64) and value[k].  svb_select_batch answers q selects: list[k]
+ * and idx[k] (uint64) give value[k].  One wave decodes the one segment that
+ * holds each answer.  A query naming a list >= m, or a select position past
+ * its list's end, gets pos = UINT64_MAX and value 0 and sets the device word
+ * err (may be NULL) to SVB_QUERY_OUT_OF_RANGE.  Asynchronous on `stream`.
+ * svb_seek_index_destroy frees the index (after the device is done with it).
+ */
+int svb_seek_index_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                          const uint8_t *in, const uint32_t *starts, uint64_t total_ints, void **index,
+                          void *stream);
+int svb_seek_batch(void *index, uint32_t q, const uint32_t *list, const uint32_t *target, uint64_t *pos,
+                   uint32_t *value, uint32_t *err, void *stream);
+int svb_select_batch(void *index, uint32_t q, const uint32_t *list, const uint64_t *idx, uint32_t *value,
+                     uint32_t *err, void *stream);
+int svb_seek_index_destroy(void *index);
 
 /* Message for a status code (static string). */
 const char *svb_strerror(int status);

@@ -18,7 +18,8 @@ __all__ = [
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
     "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
-    "svb_server_set_batching",
+    "svb_server_set_batching", "svb_seek_index_create", "svb_seek_batch", "svb_select_batch",
+    "svb_seek_index_destroy",
     "encode", "decode",
     "LIB_PATH",
 ]
@@ -26,6 +27,7 @@ __all__ = [
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
 SVB_BATCH_OVERFLOW = 3
+SVB_QUERY_OUT_OF_RANGE = 4
 
 _lib = None
 
@@ -67,6 +69,10 @@ def lib():
             "svb_server_destroy": (i32, [vp]),
             "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, vp, vp]),
             "svb_server_set_batching": (i32, [vp, u32, u32]),
+            "svb_seek_index_create": (i32, [u32, vp, vp, vp, vp, vp, u64, vp, vp]),
+            "svb_seek_batch": (i32, [vp, u32, vp, vp, vp, vp, vp, vp]),
+            "svb_select_batch": (i32, [vp, u32, vp, vp, vp, vp, vp]),
+            "svb_seek_index_destroy": (i32, [vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -285,6 +291,29 @@ def svb_server_set_batching(server, min_lists, max_wait_us):
 
 def svb_server_destroy(server):
     return _check(lib().svb_server_destroy(server), "svb_server_destroy")
+
+
+def svb_seek_index_create(m, counts, in_off, in_bytes, inp, starts, total_ints, stream=None):
+    """Skip index for seek/select over m resident lists; returns the handle (an int)."""
+    h = ctypes.c_void_p()
+    _check(lib().svb_seek_index_create(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp), _ptr(starts),
+                                       int(total_ints), ctypes.addressof(h), _stream(stream)),
+           "svb_seek_index_create")
+    return h.value
+
+
+def svb_seek_batch(index, q, lists, targets, pos, value, err=None, stream=None):
+    return _check(lib().svb_seek_batch(index, int(q), _ptr(lists), _ptr(targets), _ptr(pos), _ptr(value), _ptr(err),
+                                       _stream(stream)), "svb_seek_batch")
+
+
+def svb_select_batch(index, q, lists, idx, value, err=None, stream=None):
+    return _check(lib().svb_select_batch(index, int(q), _ptr(lists), _ptr(idx), _ptr(value), _ptr(err),
+                                         _stream(stream)), "svb_select_batch")
+
+
+def svb_seek_index_destroy(index):
+    return _check(lib().svb_seek_index_destroy(index), "svb_seek_index_destroy")
 
 
 def svb_server_replay(server, picks, arrivals=None, outstanding=0):

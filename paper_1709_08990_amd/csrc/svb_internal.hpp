@@ -128,6 +128,26 @@ int build_pool_index(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                      uint32_t **lbase, uint32_t *tasks, hipStream_t s);
 int serve_walk(BatchArgs &a, bool delta, hipStream_t s);
 
+// Seek and select over a task index (built by build_pool_index): per task the
+// running maximum of its list's values up to the task's segment's end.
+struct SeekArgs {
+    uint32_t m;               // lists
+    uint64_t tasks;           // segments of the index
+    const TaskDesc *desc;     // task index (no output addresses)
+    const uint32_t *lbase;    // first task of each list; lbase[m] = tasks
+    uint32_t *rmax;           // per task: running maximum (written by the index build)
+    bool delta;
+    uint32_t q;               // queries
+    const uint32_t *list;     // list of each query
+    const uint32_t *target;   // seek targets
+    const uint64_t *idx;      // select positions
+    uint64_t *pos;            // seek: out
+    uint32_t *value;          // out
+    uint32_t *err;            // flag word (required by the index build, may be null for queries)
+};
+hipError_t launch_seek_index(const SeekArgs &a, hipStream_t s);
+hipError_t launch_seek_queries(const SeekArgs &a, bool seek, hipStream_t s);
+
 // Encoding (two passes: data bytes per segment, scan, pack).
 // A stream to encode: n values at `in`; the stream (control bytes first) is
 // written at `out`.  Delta encoding starts from `start`.

@@ -1,0 +1,383 @@
+// Seek and select on resident compressed lists (the two operations on the
+// compressed stream that Section 5 benchmarks): seek(list, target) gives the
+// first position whose value is >= target, with that value; select(list, i)
+// gives the value at position i.  A value is the running sum for delta-coded
+// lists (Section 2) and the stored integer otherwise.
+//
+// Skip index, built once over the lists: the batched decoder's task index (per
+// 1024-integer segment: its byte offset in the list's data stream and the
+// running sum before it) plus, per segment, the running maximum of the list's
+// values up to the segment's end.  The running maximum never decreases, so the
+// segment holding a seek's answer is the first whose running maximum reaches
+// the target, found by a 64-way search, whether or not the list is sorted;
+// select's segment is i / 1024.  Each query is one wave that decodes that one
+// segment with the single-stream decoder's segment code.
+#include "svb_device.hpp"
+#include "svb_internal.hpp"
+#include "svb_segment.hpp"
+
+namespace svb {
+
+namespace {
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32) | (uint64_t)uniform32((uint32_t)x);
+}
+
+// Inclusive running maximum over the 64 lanes of a wave (the DPP pattern of
+// wave_incl_scan with max in place of +; lanes that a step does not reach see
+// 0, which leaves the maximum of unsigned values unchanged).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, true));   // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, true));   // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, true));   // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, true));   // row_shr:8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+#pragma unroll
+    for (uint32_t o = kWave / 2; o >= 1; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, kWave));
+    return x;
+}
+
+// One segment of one list, as the task index describes it (wave-uniform).
+struct SegRef {
+    DecodeArgs p;
+    uint64_t s;
+    uint64_t boff;
+    uint32_t carry;
+};
+
+__device__ __forceinline__ SegRef load_seg(const TaskDesc *desc, uint64_t t) {
+    const TaskDesc d = desc[t];
+    SegRef r;
+    r.p = DecodeArgs{};
+    r.p.in = (const uint8_t *)uniform64(d.in);
+    r.p.in_bytes = uniform64(d.in_bytes);
+    r.p.n = uniform64(d.n);
+    r.s = uniform32(d.s);
+    r.boff = uniform64(d.boff);
+    r.carry = uniform32(d.carry);
+    return r;
+}
+
+// Decodes the segment into the lane's 16 values (block 64 k + lane, integer j
+// in v[k][j]; integers past the list's end read as 0).  Returns true if the
+// segment's data run past the list's bytes (corrupt input; the values are then
+// meaningless, and no load left the list's bytes).
+__device__ __forceinline__ bool decode_seg(const SegRef &r, bool delta, uint8_t *stage, uint32_t lane,
+                                           uint32_t (&v)[4][4]) {
+    const SegCtrl sc = load_seg_ctrl(r.p, r.s, lane);
+    const SegPlan plan = plan_segment(r.p, r.s, sc, lane);
+    const uint64_t nblocks = (r.p.n + 3) >> 2;
+    const uint8_t *q = r.p.in + nblocks + r.boff;
+    Span sp;
+    const uint32_t sh16 = (uint32_t)((uintptr_t)q & 15u);
+    sp.abase = q - sh16;
+    sp.nch = (sh16 + plan.total + 15) >> 4;
+    const bool corrupt = r.boff + plan.total > r.p.in_bytes - nblocks;
+    span_load(r.p, sp, lane);
+    span_to_lds(r.p, sp, stage, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    extract_segment(r.p, r.s, stage, plan, sh16, lane, v);
+    if (delta) {
+        uint32_t carry = r.carry;
+        running_sum(v, carry);
+    }
+    return corrupt;
+}
+
+// The value at local position li (0..1023) of a decoded segment, on every lane.
+__device__ __forceinline__ uint32_t value_at(const uint32_t (&v)[4][4], uint32_t li) {
+    const uint32_t k = li >> 8, j = li & 3u, owner = (li >> 2) & (kWave - 1);
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (uint32_t jj = 0; jj < 4; ++jj)
+            if (kk == k && jj == j) mine = v[kk][jj];
+    return (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)owner);
+}
+
+// Index build, pass 1: the largest value of every segment (one wave per task).
+__global__ __launch_bounds__(kThreads) void seg_max_kernel(SeekArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wave;
+    if (t >= a.tasks) return;
+    const SegRef r = load_seg(a.desc, t);
+    uint32_t v[4][4];
+    const bool corrupt = decode_seg(r, a.delta, s_stage + wave * kStageBytes, lane, v);
+    uint32_t x = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) x = max(x, v[k][j]);  // integers past the end are 0
+    x = wave_incl_max(x);
+    if (lane == kWave - 1) a.rmax[t] = x;
+    if (corrupt && lane == 0) *a.err = SVB_DECODE_CORRUPT;
+}
+
+// Index build, pass 2: within each list, the running maximum of the segment
+// maxima (one wave per list, 64 segments per step).
+__global__ __launch_bounds__(kThreads) void run_max_kernel(SeekArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t l = (uint64_t)blockIdx.x * kWaves + wave;
+    if (l >= a.m) return;
+    const uint32_t first = a.lbase[l], end = a.lbase[l + 1];
+    uint32_t carry = 0;
+    for (uint32_t b = first; b < end; b += kWave) {
+        const uint32_t t = b + lane;
+        uint32_t x = t < end ? a.rmax[t] : 0u;
+        x = max(wave_incl_max(x), carry);
+        if (t < end) a.rmax[t] = x;
+        carry = (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
+    }
+}
+
+// Marks query `qi` as refused.
+__device__ __forceinline__ void refuse(const SeekArgs &a, uint32_t qi, uint32_t code, uint32_t lane) {
+    if (lane != 0) return;
+    if (a.pos) a.pos[qi] = ~0ull;
+    a.value[qi] = 0u;
+    if (a.err) *a.err = code;
+}
+
+// One query per wave.  SEEK: the first position of list[qi] whose value is >=
+// target[qi] (the list's length if none, value 0).  Otherwise select: the
+// value at position idx[qi].  A list id past m, or a select position past the
+// list's end, is refused with SVB_QUERY_OUT_OF_RANGE.
+template <bool SEEK>
+__global__ __launch_bounds__(kThreads) void query_kernel(SeekArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t qi = blockIdx.x * kWaves + wave;
+    if (qi >= a.q) return;
+    const uint32_t l = uniform32(a.list[qi]);
+    if (l >= a.m) {
+        refuse(a, qi, SVB_QUERY_OUT_OF_RANGE, lane);
+        return;
+    }
+    const uint32_t first = uniform32(a.lbase[l]);
+    const uint32_t segs = uniform32(a.lbase[l + 1]) - first;
+    uint64_t s;
+    uint32_t target = 0;
+    uint64_t idx = 0;
+    if (SEEK) {
+        target = uniform32(a.target[qi]);
+        if (segs == 0 || uniform32(a.rmax[first + segs - 1]) < target) {
+            // no value reaches the target: the list's length
+            if (lane == 0) {
+                a.pos[qi] = segs ? a.desc[first].n : 0ull;
+                a.value[qi] = 0u;
+            }
+            return;
+        }
+        // the first segment whose running maximum reaches the target lies in
+        // [lo, hi]; each step probes 64 evenly spaced segments of the range
+        uint32_t lo = 0, hi = segs - 1;
+        while (lo < hi) {
+            const uint32_t step = (hi - lo + kWave) / kWave;  // ceil((hi - lo + 1) / 64)
+            const uint32_t p = lo + lane * step;
+            const bool valid = p <= hi;
+            const bool below = valid && a.rmax[first + p] < target;
+            const uint32_t g = __builtin_popcountll(__ballot(below));  // probes below the target
+            const uint32_t nvalid = __builtin_popcountll(__ballot(valid));
+            const uint32_t new_lo = g ? lo + (g - 1) * step + 1 : lo;
+            const uint32_t new_hi = g < nvalid ? lo + g * step : hi;
+            lo = new_lo;
+            hi = new_hi;
+        }
+        s = lo;
+    } else {
+        idx = uniform64(a.idx[qi]);
+        const uint64_t n = segs ? uniform64(a.desc[first].n) : 0ull;
+        if (idx >= n) {
+            refuse(a, qi, SVB_QUERY_OUT_OF_RANGE, lane);
+            return;
+        }
+        s = idx / kSegInts;
+    }
+    const SegRef r = load_seg(a.desc, first + s);
+    uint32_t v[4][4];
+    if (decode_seg(r, a.delta, s_stage + wave * kStageBytes, lane, v)) {
+        refuse(a, qi, SVB_DECODE_CORRUPT, lane);
+        return;
+    }
+    uint32_t li;
+    if (SEEK) {
+        // the segment holds a value >= target (its running maximum reaches the
+        // target, the previous segment's does not): the first one
+        const uint64_t base = s * kSegInts;
+        li = ~0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t c = 4 * (kWave * k + lane) + j;
+                if (li == ~0u && base + c < r.p.n && v[k][j] >= target) li = c;
+            }
+        li = wave_min(li);
+    } else {
+        li = (uint32_t)(idx - s * kSegInts);
+    }
+    const uint32_t val = value_at(v, li);
+    if (lane == 0) {
+        if (SEEK) a.pos[qi] = s * kSegInts + li;
+        a.value[qi] = val;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_seek_index(const SeekArgs &a, hipStream_t s) {
+    if (a.tasks)
+        hipLaunchKernelGGL(seg_max_kernel, dim3((uint32_t)((a.tasks + kWaves - 1) / kWaves)), dim3(kThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(run_max_kernel, dim3((a.m + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_seek_queries(const SeekArgs &a, bool seek, hipStream_t s) {
+    if (a.q == 0) return hipSuccess;
+    const dim3 grid((a.q + kWaves - 1) / kWaves);
+    if (seek)
+        hipLaunchKernelGGL(query_kernel<true>, grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(query_kernel<false>, grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace svb
+
+// ---------------------------------------------------------------- C ABI
+
+namespace {
+
+struct SeekIndex {
+    int device = 0;
+    uint32_t m = 0;
+    bool delta = false;
+    uint32_t tasks = 0;
+    svb::TaskDesc *desc = nullptr;
+    uint32_t *lbase = nullptr;
+    uint32_t *rmax = nullptr;
+};
+
+void free_index(SeekIndex *x) {
+    if (!x) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(x->device);
+    (void)hipDeviceSynchronize();
+    if (x->desc) (void)hipFree(x->desc);
+    if (x->lbase) (void)hipFree(x->lbase);
+    if (x->rmax) (void)hipFree(x->rmax);
+    (void)hipSetDevice(cur);
+    delete x;
+}
+
+bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+int queries(void *index, uint32_t q, const uint32_t *list, const uint32_t *target, const uint64_t *idx,
+            uint64_t *pos, uint32_t *value, uint32_t *err, bool seek, void *stream) {
+    SeekIndex *x = (SeekIndex *)index;
+    if (!x) return SVB_ERR_INVALID;
+    if (q == 0) return SVB_OK;
+    if (!list || !value || (seek ? (!target || !pos) : !idx)) return SVB_ERR_INVALID;
+    if (!aligned(list, 4) || !aligned(value, 4) || (target && !aligned(target, 4)) || (idx && !aligned(idx, 8)) ||
+        (pos && !aligned(pos, 8)) || (err && !aligned(err, 4)))
+        return SVB_ERR_INVALID;
+    if (q > (1u << 31)) return SVB_ERR_INVALID;
+    svb::SeekArgs a = {};
+    a.m = x->m;
+    a.tasks = x->tasks;
+    a.desc = x->desc;
+    a.lbase = x->lbase;
+    a.rmax = x->rmax;
+    a.delta = x->delta;
+    a.q = q;
+    a.list = list;
+    a.target = target;
+    a.idx = idx;
+    a.pos = seek ? pos : nullptr;
+    a.value = value;
+    a.err = err;
+    return svb::launch_seek_queries(a, seek, (hipStream_t)stream) == hipSuccess ? SVB_OK : SVB_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int svb_seek_index_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
+                          const uint8_t *in, const uint32_t *starts, uint64_t total_ints, void **index,
+                          void *stream) {
+    if (!index) return SVB_ERR_INVALID;
+    *index = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    SeekIndex *x = new SeekIndex();
+    (void)hipGetDevice(&x->device);
+    x->m = m;
+    x->delta = starts != nullptr;
+    int st = svb::build_pool_index(m, counts, in_off, in_bytes, in, starts, total_ints, &x->desc, &x->lbase,
+                                   &x->tasks, s);
+    uint32_t *d_err = nullptr;
+    if (st == SVB_OK && hipMalloc((void **)&x->rmax, 4ull * (x->tasks ? x->tasks : 1)) != hipSuccess)
+        st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && hipMalloc((void **)&d_err, 4) != hipSuccess) st = SVB_ERR_NOMEM;
+    uint32_t h_err = 0;
+    if (st == SVB_OK) {
+        svb::SeekArgs a = {};
+        a.m = m;
+        a.tasks = x->tasks;
+        a.desc = x->desc;
+        a.lbase = x->lbase;
+        a.rmax = x->rmax;
+        a.delta = x->delta;
+        a.err = d_err;
+        if (svb::launch_fill(d_err, 1, 0u, s) != hipSuccess || svb::launch_seek_index(a, s) != hipSuccess ||
+            hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = SVB_ERR_HIP;
+        else if (h_err != 0)
+            st = SVB_ERR_INVALID;
+    }
+    if (d_err) (void)hipFree(d_err);
+    if (st != SVB_OK) {
+        free_index(x);
+        return st;
+    }
+    *index = x;
+    return SVB_OK;
+}
+
+int svb_seek_batch(void *index, uint32_t q, const uint32_t *list, const uint32_t *target, uint64_t *pos,
+                   uint32_t *value, uint32_t *err, void *stream) {
+    return queries(index, q, list, target, nullptr, pos, value, err, true, stream);
+}
+
+int svb_select_batch(void *index, uint32_t q, const uint32_t *list, const uint64_t *idx, uint32_t *value,
+                     uint32_t *err, void *stream) {
+    return queries(index, q, list, nullptr, idx, nullptr, value, err, false, stream);
+}
+
+int svb_seek_index_destroy(void *index) {
+    free_index((SeekIndex *)index);
+    return SVB_OK;
+}
+
+}  // extern "C"
