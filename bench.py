@@ -25,6 +25,9 @@ Prints one JSON line.  Besides the headline it carries:
                 rate, against one array of the same integers (the lists back
                 to back, one stream) and against one svb_delta_decode call
                 per list;
+  seek_select   seek and select over 2^20 lists of 256 running sums (deltas
+                below 2^8 and 2^16), 2^22 queries per call, queries/s and
+                algorithmic GB/s, the oracle's walk timed beside them;
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
@@ -395,6 +398,94 @@ def measure_batched(svb, torch, np, inputs, steps, warmup, per_list=True):
     return res
 
 
+def measure_seek(svb, torch, np, inputs, steps, warmup, oracle_sample=20_000):
+    """Seek and select (Section 5's operations on compressed lists) at GPU scale: the paper's
+    workload of lists of 256 running sums of deltas below 2^b, 2^20 lists, one call answering 2^22
+    random queries (a uniform list, a uniform target in [0, last + 2) or a uniform position).
+    Algorithmic bytes of a query: its inputs and outputs, the index entries it reads (list bases,
+    the running maximum, the segment's 64-byte descriptor) and the segment it decodes (control
+    and data bytes).  The answers are checked on a sample against the input lists (sorted, so seek
+    is numpy's lower bound); the oracle is only timed, as this section's CPU baseline."""
+    import oracle
+    out = {}
+    m, q = 1 << 20, 1 << 22
+    cap = svb.svb_max_compressed_bytes(256)
+    u64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+    for bits in (8, 16):
+        vals, offs = inputs.seek_lists(m, bits, seed=90 + bits)
+        x_dev = torch.from_numpy(vals.view(np.int32)).cuda()
+        counts = np.full(m, 256, dtype=np.uint64)
+        byte_off = np.arange(m, dtype=np.uint64) * cap
+        comp = torch.empty(m * cap, dtype=torch.uint8, device="cuda")
+        sizes = torch.empty(m, dtype=torch.int64, device="cuda")
+        starts = torch.zeros(m, dtype=torch.int32, device="cuda")
+        d_counts, d_val_off = u64(counts), u64(offs[:-1])
+        svb.svb_encode_batch(m, d_counts, d_val_off, x_dev, u64(byte_off), comp, sizes, starts, 256 * m)
+        torch.cuda.synchronize()
+        # the streams packed back to back, as an index over stored lists holds them (encoded again at
+        # their final offsets)
+        h_sizes = sizes.cpu().numpy().view(np.uint64).copy()
+        byte_off = np.zeros(m, dtype=np.uint64)
+        np.cumsum(h_sizes[:-1], out=byte_off[1:])
+        del comp
+        comp = torch.empty(int(h_sizes.sum()) + 64, dtype=torch.uint8, device="cuda")
+        d_off = u64(byte_off)
+        svb.svb_encode_batch(m, d_counts, d_val_off, x_dev, d_off, comp, sizes, starts, 256 * m)
+        torch.cuda.synchronize()
+        seg_bytes = float(h_sizes.mean())
+        t0 = time.perf_counter()
+        index = svb.svb_seek_index_create(m, d_counts, d_off, sizes, comp, starts, 256 * m)
+        build_s = time.perf_counter() - t0
+        ids, targets, idx = inputs.seek_queries(vals, offs, q, seed=95 + bits)
+        d_ids, d_t, d_i = torch.from_numpy(ids.view(np.int32)).cuda(), torch.from_numpy(targets.view(np.int32)).cuda(), \
+            u64(idx)
+        pos = torch.empty(q, dtype=torch.int64, device="cuda")
+        val = torch.empty(q, dtype=torch.int32, device="cuda")
+        sval = torch.empty(q, dtype=torch.int32, device="cuda")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        swall, skms = timed_steps(svb, torch, lambda: svb.svb_seek_batch(index, q, d_ids, d_t, pos, val, err), steps,
+                                  warmup)
+        lwall, lkms = timed_steps(svb, torch, lambda: svb.svb_select_batch(index, q, d_ids, d_i, sval, err), steps,
+                                  warmup)
+        ok = int(err.item()) == 0
+        pos_h, val_h, sval_h = pos.cpu().numpy(), val.cpu().numpy().view(np.uint32), sval.cpu().numpy().view(np.uint32)
+        rng = np.random.default_rng(bits)
+        sample = rng.integers(0, q, size=oracle_sample)
+        for k in sample[:2_000]:
+            x = vals[offs[ids[k]]:offs[ids[k] + 1]]
+            p = int(np.searchsorted(x, targets[k], side="left"))
+            ok &= (int(pos_h[k]), int(val_h[k])) == (p, int(x[p]) if p < x.size else 0)
+            ok &= int(sval_h[k]) == int(x[idx[k]])
+        # CPU baseline of this section: the oracle's walk over the sampled queries (one ctypes call each)
+        host_streams = comp.cpu().numpy().view(np.uint8)
+        t0 = time.perf_counter()
+        for k in sample:
+            l = int(ids[k])
+            o = int(byte_off[l])
+            oracle.seek(host_streams[o:o + int(h_sizes[l])], 256, int(targets[k]), True, 0)
+        oracle_s = time.perf_counter() - t0
+        svb.svb_seek_index_destroy(index)
+        q_in_out = 4 + 4 + 8 + 4           # list id, target, position, value
+        index_bytes = 8 + 4 + 64           # list bases, running maximum, descriptor
+        per_query = q_in_out + index_bytes + seg_bytes
+        seek_ms, sel_ms = 1e3 * swall / steps, 1e3 * lwall / steps
+        out["b%d" % bits] = {
+            "lists": m, "ints_per_list": 256, "queries_per_call": q, "stream_bytes_per_list": seg_bytes,
+            "index_build_s": build_s,
+            "seek": {"ms_per_call": seek_ms, "queries_per_s": q / (seek_ms * 1e-3),
+                     "alg_bytes_per_query": per_query, "GBps": gbs(per_query * q, seek_ms),
+                     "frac_of_peak": gbs(per_query * q, seek_ms) / HBM_PEAK_GBS, "kernels_ms": skms},
+            "select": {"ms_per_call": sel_ms, "queries_per_s": q / (sel_ms * 1e-3),
+                       "alg_bytes_per_query": per_query, "GBps": gbs(per_query * q, sel_ms),
+                       "frac_of_peak": gbs(per_query * q, sel_ms) / HBM_PEAK_GBS, "kernels_ms": lkms},
+            "cpu_oracle": {"queries_per_s": oracle_sample / oracle_s, "cores": 1, "kind": "oracle",
+                           "sample": "%d seeks, one ctypes call each (call overhead included)" % oracle_sample},
+            "sample_matches_input": bool(ok)}
+        del x_dev, comp, host_streams
+        torch.cuda.empty_cache()
+    return out
+
+
 def build_pool(svb, torch, np, inputs, m, total, cap, seed):
     """Serving pool: m delta-coded posting lists (rank-size Zipf lengths in [1, cap] summing to
     `total`, sorted sets over [0, 2^31) drawn on the GPU), encoded by the batched encoder and
@@ -571,6 +662,7 @@ def main():
     ap.add_argument("--no-2p28", action="store_true", help="skip the 2^28 sub-measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 200,000-list batched measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-seek", action="store_true", help="skip the seek/select measurement")
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -578,11 +670,11 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
                     "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving")
+                    "--no-2p28 --no-batched --no-serving --no-seek")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
                     "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving")
+                    "--no-2p28 --no-batched --no-serving --no-seek")
     ap.add_argument("--trace-bench-json", default=None,
                     help="bench line printed by the traced command (for --summarize-trace)")
     args = ap.parse_args()
@@ -680,6 +772,14 @@ def main():
         line["batched"] = rb
         log("batched delta decode %.4f ms/call, %.3g ints/s (%.2fx single array; %.2fx one array of the same ints)"
             % (rb["ms_per_call"], rb["uint32_per_s"], rb["vs_single_array"], rb["vs_single_array_same_ints"]))
+    if not args.no_seek:
+        log("seek/select: 2^20 lists of 256 integers, 2^22 queries per call")
+        rk = measure_seek(svb, torch, np, inputs, max(5, args.steps // 2), 2)
+        assert all(r["sample_matches_input"] for r in rk.values()), "seek/select mismatch"
+        line["seek_select"] = rk
+        for b, r in rk.items():
+            log("seek %s: %.3g queries/s (%.1f%% of HBM peak), select %.3g queries/s"
+                % (b, r["seek"]["queries_per_s"], 100 * r["seek"]["frac_of_peak"], r["select"]["queries_per_s"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)

@@ -138,6 +138,7 @@ struct SeekArgs {
     uint32_t *rmax;           // per task: running maximum (written by the index build)
     bool delta;
     uint32_t q;               // queries
+    uint32_t chunk;           // queries per wave
     const uint32_t *list;     // list of each query
     const uint32_t *target;   // seek targets
     const uint64_t *idx;      // select positions

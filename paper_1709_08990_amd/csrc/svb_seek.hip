@@ -12,6 +12,8 @@
 // the target, found by a 64-way search, whether or not the list is sorted;
 // select's segment is i / 1024.  Each query is one wave that decodes that one
 // segment with the single-stream decoder's segment code.
+#include <algorithm>
+
 #include "svb_device.hpp"
 #include "svb_internal.hpp"
 #include "svb_segment.hpp"
@@ -154,17 +156,15 @@ __device__ __forceinline__ void refuse(const SeekArgs &a, uint32_t qi, uint32_t 
     if (a.err) *a.err = code;
 }
 
-// One query per wave.  SEEK: the first position of list[qi] whose value is >=
-// target[qi] (the list's length if none, value 0).  Otherwise select: the
-// value at position idx[qi].  A list id past m, or a select position past the
-// list's end, is refused with SVB_QUERY_OUT_OF_RANGE.
+// Query qi, answered by one wave.  SEEK: the first position of list[qi] whose
+// value is >= target[qi] (the list's length if none, value 0).  Otherwise
+// select: the value at position idx[qi].  A list id past m, or a select
+// position past the list's end, is refused with SVB_QUERY_OUT_OF_RANGE.
 template <bool SEEK>
-__global__ __launch_bounds__(kThreads) void query_kernel(SeekArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint32_t qi = blockIdx.x * kWaves + wave;
-    if (qi >= a.q) return;
+__device__ __forceinline__ void answer(const SeekArgs &a, uint32_t qi, uint8_t *stage, uint32_t lane) {
+    // the query's list and its target or position are requested together
+    const uint32_t t_raw = SEEK ? a.target[qi] : 0u;
+    const uint64_t i_raw = SEEK ? 0ull : a.idx[qi];
     const uint32_t l = uniform32(a.list[qi]);
     if (l >= a.m) {
         refuse(a, qi, SVB_QUERY_OUT_OF_RANGE, lane);
@@ -175,12 +175,24 @@ __global__ __launch_bounds__(kThreads) void query_kernel(SeekArgs a) {
     uint64_t s;
     uint32_t target = 0;
     uint64_t idx = 0;
+    SegRef r;
     if (SEEK) {
-        target = uniform32(a.target[qi]);
-        if (segs == 0 || uniform32(a.rmax[first + segs - 1]) < target) {
+        target = uniform32(t_raw);
+        if (segs == 0) {
+            if (lane == 0) {
+                a.pos[qi] = 0ull;
+                a.value[qi] = 0u;
+            }
+            return;
+        }
+        // the list's largest value and its first segment's descriptor are
+        // requested together (a list of one segment needs nothing else)
+        const uint32_t top_raw = a.rmax[first + segs - 1];
+        r = load_seg(a.desc, first);
+        if (uniform32(top_raw) < target) {
             // no value reaches the target: the list's length
             if (lane == 0) {
-                a.pos[qi] = segs ? a.desc[first].n : 0ull;
+                a.pos[qi] = r.p.n;
                 a.value[qi] = 0u;
             }
             return;
@@ -193,26 +205,31 @@ __global__ __launch_bounds__(kThreads) void query_kernel(SeekArgs a) {
             const uint32_t p = lo + lane * step;
             const bool valid = p <= hi;
             const bool below = valid && a.rmax[first + p] < target;
-            const uint32_t g = __builtin_popcountll(__ballot(below));  // probes below the target
+            const uint32_t n_below = __builtin_popcountll(__ballot(below));
             const uint32_t nvalid = __builtin_popcountll(__ballot(valid));
-            const uint32_t new_lo = g ? lo + (g - 1) * step + 1 : lo;
-            const uint32_t new_hi = g < nvalid ? lo + g * step : hi;
+            const uint32_t new_lo = n_below ? lo + (n_below - 1) * step + 1 : lo;
+            const uint32_t new_hi = n_below < nvalid ? lo + n_below * step : hi;
             lo = new_lo;
             hi = new_hi;
         }
         s = lo;
+        if (s) r = load_seg(a.desc, first + s);
     } else {
-        idx = uniform64(a.idx[qi]);
-        const uint64_t n = segs ? uniform64(a.desc[first].n) : 0ull;
-        if (idx >= n) {
+        // every segment's descriptor holds the list's length
+        idx = uniform64(i_raw);
+        s = idx / kSegInts;
+        if (s >= segs) {
             refuse(a, qi, SVB_QUERY_OUT_OF_RANGE, lane);
             return;
         }
-        s = idx / kSegInts;
+        r = load_seg(a.desc, first + s);
+        if (idx >= r.p.n) {
+            refuse(a, qi, SVB_QUERY_OUT_OF_RANGE, lane);
+            return;
+        }
     }
-    const SegRef r = load_seg(a.desc, first + s);
     uint32_t v[4][4];
-    if (decode_seg(r, a.delta, s_stage + wave * kStageBytes, lane, v)) {
+    if (decode_seg(r, a.delta, stage, lane, v)) {
         refuse(a, qi, SVB_DECODE_CORRUPT, lane);
         return;
     }
@@ -240,6 +257,30 @@ __global__ __launch_bounds__(kThreads) void query_kernel(SeekArgs a) {
     }
 }
 
+// Each wave answers a run of a.chunk consecutive queries, so that a large
+// batch does not cost one workgroup launch per four queries.  Throughput
+// follows the number of resident waves (each query is a chain of dependent
+// loads), so the kernel is held to eight waves per SIMD.  (Keeping the next
+// queries' index loads in flight while one decodes was measured no faster:
+// it cost more registers, hence waves, than it saved in waiting.)
+template <bool SEEK>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void query_kernel(SeekArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t q0 = ((uint64_t)blockIdx.x * kWaves + wave) * a.chunk;
+    const uint64_t q1 = q0 + a.chunk < a.q ? q0 + a.chunk : a.q;
+    uint8_t *stage = s_stage + wave * kStageBytes;
+#pragma unroll 1
+    for (uint64_t qi = q0; qi < q1; ++qi) {
+        answer<SEEK>(a, (uint32_t)qi, stage, lane);
+        // the next query overwrites the staging area: LDS operations of a wave
+        // complete in order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_seek_index(const SeekArgs &a, hipStream_t s) {
@@ -252,8 +293,9 @@ hipError_t launch_seek_index(const SeekArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_seek_queries(const SeekArgs &a, bool seek, hipStream_t s) {
-    if (a.q == 0) return hipSuccess;
-    const dim3 grid((a.q + kWaves - 1) / kWaves);
+    if (a.q == 0 || a.chunk == 0) return hipSuccess;
+    const uint64_t waves = (a.q + a.chunk - 1) / a.chunk;
+    const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves));
     if (seek)
         hipLaunchKernelGGL(query_kernel<true>, grid, dim3(kThreads), 0, s, a);
     else
@@ -310,6 +352,8 @@ int queries(void *index, uint32_t q, const uint32_t *list, const uint32_t *targe
     a.rmax = x->rmax;
     a.delta = x->delta;
     a.q = q;
+    // queries per wave: one while that still leaves tens of thousands of waves
+    a.chunk = std::min<uint32_t>(16u, std::max<uint32_t>(1u, q / 32768u));
     a.list = list;
     a.target = target;
     a.idx = idx;
