@@ -105,20 +105,34 @@ struct Span {
     u32x4a w[5];
 };
 
+// The tests are wave-uniform where they can be: slots wholly past the span
+// are skipped, and a span that lies inside the buffer (every segment's but
+// possibly a stream's first and last) loads its chunks without a per-chunk
+// bounds test.  The register and address work of slots and tests is a large
+// share of a segment's instructions, and the value-sum pass is bound by
+// instruction issue.
 __device__ __forceinline__ void span_load(const DecodeArgs &p, Span &sp, uint32_t lane) {
     const uint8_t *hi = p.in + p.in_bytes;
+    const bool inside = sp.abase >= p.in && sp.abase + 16ull * sp.nch <= hi;
 #pragma unroll
     for (uint32_t i = 0; i < 5; ++i) {
+        if (kWave * i >= sp.nch) break;
         const uint32_t c = lane + kWave * i;
         const uint8_t *cp = sp.abase + 16 * c;
-        sp.w[i] = u32x4a{0u, 0u, 0u, 0u};
-        if (c < sp.nch && cp < hi && cp + 16 > p.in) sp.w[i] = *gptr((const u32x4a *)cp);
+        if (inside) {
+            if (c < sp.nch) sp.w[i] = *gptr((const u32x4a *)cp);
+        } else {
+            sp.w[i] = u32x4a{0u, 0u, 0u, 0u};
+            if (c < sp.nch && cp < hi && cp + 16 > p.in) sp.w[i] = *gptr((const u32x4a *)cp);
+        }
     }
 }
 
+// Stages the chunks below nch (only those span_load filled).
 __device__ __forceinline__ void span_to_lds(const DecodeArgs &, const Span &sp, uint8_t *stage, uint32_t lane) {
 #pragma unroll
     for (uint32_t i = 0; i < 5; ++i) {
+        if (kWave * i >= sp.nch) break;
         const uint32_t c = lane + kWave * i;
         if (c < sp.nch) *(u32x4a *)(stage + kStagePad + 16 * c) = sp.w[i];
     }
