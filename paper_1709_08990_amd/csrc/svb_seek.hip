@@ -98,6 +98,68 @@ __device__ __forceinline__ bool decode_seg(const SegRef &r, bool delta, uint8_t 
     return corrupt;
 }
 
+// A segment of at most 256 integers (a short list, or a list's last segment)
+// uses one row of the four: lane l holds block l only.  Decoding just that row
+// saves three quarters of the scans, extraction and comparisons, and queries
+// are bound by instruction issue.  v[j] is integer 4 lane + j (0 past the
+// end).
+__device__ __forceinline__ bool decode_row(const SegRef &r, uint32_t rem, bool delta, uint8_t *stage, uint32_t lane,
+                                           uint32_t (&v)[4]) {
+    const uint64_t nblocks = (r.p.n + 3) >> 2;
+    const uint32_t nb_seg = (rem + 3) >> 2;  // control bytes of the segment (1..64)
+    const int32_t left = (int32_t)rem - (int32_t)(4 * lane);
+    const uint32_t m = left <= 0 ? 0u : (left >= 4 ? 4u : (uint32_t)left);
+    const uint64_t b = r.s * kSegCtrl + (lane < nb_seg ? lane : nb_seg - 1);
+    const uint32_t raw = gptr(r.p.in)[b];
+    const uint32_t c = m ? (raw & ((1u << (2 * m)) - 1u)) : 0u;
+    const uint32_t nb = m + __builtin_popcount(c) + __builtin_popcount(c & 0xAAu);
+    const uint32_t incl = wave_incl_scan(nb);
+    const uint32_t total = wave_last(incl);
+    const uint8_t *q = r.p.in + nblocks + r.boff;
+    Span sp;
+    const uint32_t sh16 = (uint32_t)((uintptr_t)q & 15u);
+    sp.abase = q - sh16;
+    sp.nch = (sh16 + total + 15) >> 4;
+    const bool corrupt = r.boff + total > r.p.in_bytes - nblocks;
+    span_load(r.p, sp, lane);
+    span_to_lds(r.p, sp, stage, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // as extract_segment, for the one row
+    uint32_t R = kStagePad - 4 + sh16 + (incl - nb);
+    const uint32_t nc = ~c;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t y = (nc >> (2 * j)) & 3u;
+        R -= y;
+        const uint32_t a = (R & ~3u) + 4 * (j + 1);
+        const uint32_t lo = *(const uint32_t *)(stage + a);
+        const uint32_t hi = *(const uint32_t *)(stage + a + 4);
+        v[j] = j < m ? __builtin_amdgcn_alignbyte(0u, __builtin_amdgcn_alignbyte(hi, lo, R & 3u), y) : 0u;
+    }
+    if (delta) {
+        v[1] += v[0];
+        v[2] += v[1];
+        v[3] += v[2];
+        const uint32_t li = wave_incl_scan(v[3]);
+        const uint32_t add = r.carry + li - v[3];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) v[j] += add;
+    }
+    return corrupt;
+}
+
+// The value at local position li (0..255) of a decoded row, on every lane.
+__device__ __forceinline__ uint32_t row_value_at(const uint32_t (&v)[4], uint32_t li) {
+    const uint32_t j = li & 3u, owner = (li >> 2) & (kWave - 1);
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4; ++jj)
+        if (jj == j) mine = v[jj];
+    return (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)owner);
+}
+
 // The value at local position li (0..1023) of a decoded segment, on every lane.
 __device__ __forceinline__ uint32_t value_at(const uint32_t (&v)[4][4], uint32_t li) {
     const uint32_t k = li >> 8, j = li & 3u, owner = (li >> 2) & (kWave - 1);
@@ -228,31 +290,53 @@ __device__ __forceinline__ void answer(const SeekArgs &a, uint32_t qi, uint8_t *
             return;
         }
     }
-    uint32_t v[4][4];
-    if (decode_seg(r, a.delta, stage, lane, v)) {
-        refuse(a, qi, SVB_DECODE_CORRUPT, lane);
-        return;
-    }
-    uint32_t li;
-    if (SEEK) {
-        // the segment holds a value >= target (its running maximum reaches the
-        // target, the previous segment's does not): the first one
-        const uint64_t base = s * kSegInts;
-        li = ~0u;
-#pragma unroll
-        for (uint32_t k = 0; k < 4; ++k)
+    const uint64_t base = s * kSegInts;
+    const uint64_t rem64 = r.p.n - base;
+    uint32_t li, val;
+    if (rem64 <= kSegInts / 4) {
+        // a segment of one row
+        uint32_t v[4];
+        if (decode_row(r, (uint32_t)rem64, a.delta, stage, lane, v)) {
+            refuse(a, qi, SVB_DECODE_CORRUPT, lane);
+            return;
+        }
+        if (SEEK) {
+            li = ~0u;
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t c = 4 * (kWave * k + lane) + j;
-                if (li == ~0u && base + c < r.p.n && v[k][j] >= target) li = c;
+                const uint32_t c = 4 * lane + j;
+                if (li == ~0u && c < rem64 && v[j] >= target) li = c;
             }
-        li = wave_min(li);
+            li = wave_min(li);
+        } else {
+            li = (uint32_t)(idx - base);
+        }
+        val = row_value_at(v, li);
     } else {
-        li = (uint32_t)(idx - s * kSegInts);
+        uint32_t v[4][4];
+        if (decode_seg(r, a.delta, stage, lane, v)) {
+            refuse(a, qi, SVB_DECODE_CORRUPT, lane);
+            return;
+        }
+        if (SEEK) {
+            // the segment holds a value >= target (its running maximum reaches
+            // the target, the previous segment's does not): the first one
+            li = ~0u;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t c = 4 * (kWave * k + lane) + j;
+                    if (li == ~0u && base + c < r.p.n && v[k][j] >= target) li = c;
+                }
+            li = wave_min(li);
+        } else {
+            li = (uint32_t)(idx - base);
+        }
+        val = value_at(v, li);
     }
-    const uint32_t val = value_at(v, li);
     if (lane == 0) {
-        if (SEEK) a.pos[qi] = s * kSegInts + li;
+        if (SEEK) a.pos[qi] = base + li;
         a.value[qi] = val;
     }
 }
