@@ -43,10 +43,15 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+// The first of a lane's four integers (j = 0..3, in order) that is a valid
+// position with a value >= target, or 4 if none.
+__device__ __forceinline__ uint32_t first_at_least(const uint32_t (&v)[4], uint32_t valid_n, uint32_t c0,
+                                                   uint32_t target) {
+    uint32_t jf = 4;
 #pragma unroll
-    for (uint32_t o = kWave / 2; o >= 1; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, kWave));
-    return x;
+    for (int j = 3; j >= 0; --j)
+        if (c0 + (uint32_t)j < valid_n && v[j] >= target) jf = (uint32_t)j;
+    return jf;
 }
 
 // One segment of one list, as the task index describes it (wave-uniform).
@@ -301,13 +306,12 @@ __device__ __forceinline__ void answer(const SeekArgs &a, uint32_t qi, uint8_t *
             return;
         }
         if (SEEK) {
-            li = ~0u;
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t c = 4 * lane + j;
-                if (li == ~0u && c < rem64 && v[j] >= target) li = c;
-            }
-            li = wave_min(li);
+            // the row holds a value >= target: the first lane that has one,
+            // then its first such integer
+            const uint32_t jf = first_at_least(v, (uint32_t)rem64, 4 * lane, target);
+            const uint64_t mask = __ballot(jf < 4);
+            const uint32_t owner = mask ? (uint32_t)__builtin_ctzll(mask) : 0u;
+            li = 4 * owner + (uint32_t)__builtin_amdgcn_readlane((int)jf, (int)owner);
         } else {
             li = (uint32_t)(idx - base);
         }
@@ -320,16 +324,21 @@ __device__ __forceinline__ void answer(const SeekArgs &a, uint32_t qi, uint8_t *
         }
         if (SEEK) {
             // the segment holds a value >= target (its running maximum reaches
-            // the target, the previous segment's does not): the first one
-            li = ~0u;
+            // the target, the previous segment's does not): the first row
+            // with one, its first lane with one, that lane's first such integer
+            const uint32_t rem = (uint32_t)(rem64 < kSegInts ? rem64 : kSegInts);
+            li = 0;
+            bool found = false;
 #pragma unroll
-            for (uint32_t k = 0; k < 4; ++k)
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    const uint32_t c = 4 * (kWave * k + lane) + j;
-                    if (li == ~0u && base + c < r.p.n && v[k][j] >= target) li = c;
+            for (uint32_t k = 0; k < 4; ++k) {
+                const uint32_t jf = first_at_least(v[k], rem, 4 * (kWave * k + lane), target);
+                const uint64_t mask = __ballot(jf < 4);
+                if (!found && mask) {
+                    const uint32_t owner = (uint32_t)__builtin_ctzll(mask);
+                    li = 4 * (kWave * k + owner) + (uint32_t)__builtin_amdgcn_readlane((int)jf, (int)owner);
+                    found = true;
                 }
-            li = wave_min(li);
+            }
         } else {
             li = (uint32_t)(idx - base);
         }
