@@ -17,11 +17,11 @@
 //      the list's first task);
 //   4. batch_desc_kernel: one 64-byte descriptor per task (stream, output,
 //      segment, byte offset), so a wave needs a single load to start a task;
-//   5. delta decoding only: batch_walk_kernel in value-sum mode sums the
-//      stored differences of every task that is not the last of its list,
-//      then a scan, and batch_carry_kernel -> each task's carry in its
-//      descriptor (global scan minus the value at the list's first task, plus
-//      the list's start);
+//   5. delta decoding only: batch_sums_runs_kernel sums the stored
+//      differences of every task that is not the last of its list (walking
+//      each list's consecutive tasks as one run), then a scan, and
+//      batch_carry_kernel -> each task's carry in its descriptor (global scan
+//      minus the value at the list's first task, plus the list's start);
 //   6. batch_walk_kernel / batch_encode_kernel: each wave takes a run of
 //      `chunk` consecutive tasks (the tuned parameter).  The decoder keeps a
 //      pipeline three tasks deep: while one segment is decoded from LDS, the
@@ -188,13 +188,12 @@ __device__ __forceinline__ void issue_task(const TaskHdr &k, const SegCtrl &sc, 
 // deep: in the iteration that decodes task t, the data of t + 1, the control
 // bytes of t + 2 and the descriptor of t + 3 are requested, each from what the
 // previous iteration loaded.
-//   kPlain / kDelta: decode and store (delta: running sum from the task's carry);
-//   kSums: for tasks that are not the last segment of their list, write the
-//          sum of the stored differences to ivsum (other tasks are skipped).
-// Five waves per SIMD: the delta walk fits 96 registers without spilling, and
+// kPlain / kDelta: decode and store (delta: running sum from the task's
+// carry).  Five waves per SIMD: the delta walk fits 96 registers without spilling, and
 // was measured 12% faster there than at four.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_walk_kernel(BatchArgs a) {
+    static_assert(MODE == kPlain || MODE == kDelta, "the value sums walk in runs (batch_sums_runs_kernel)");
     constexpr bool DELTA = MODE == kDelta;
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -206,8 +205,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     uint8_t *stage = s_stage + wave * kStageBytes;
     bool corrupt = false;
 
-    // in the value-sum pass only tasks that are not the last of their list work
-    auto active = [&](const TaskHdr &k) { return k.valid && (MODE != kSums || !k.last); };
+    auto active = [&](const TaskHdr &k) { return k.valid; };
     TaskHdr h0 = load_hdr(a, t0, t_end);
     Pending pend;
     if (active(h0)) issue_task(h0, load_seg_ctrl(h0.p, h0.s, lane), lane, pend);
@@ -239,25 +237,70 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
         if (work) {
             uint32_t v[4][4];
             extract_segment(k.p, k.s, stage, seg, sh16, lane, v);
-            if (MODE == kSums) {
-                uint32_t x = 0;
-#pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) x += v[q][0] + v[q][1] + v[q][2] + v[q][3];
-                x = wave_last(wave_incl_scan(x));
-                if (lane == 0) a.ivsum[t] = x;
-            } else {
-                uint32_t carry = k.carry;
-                if (DELTA) running_sum(v, carry);
-                store_segment(k.p, k.s, lane, v, 0u);
-            }
-        } else if (MODE == kSums && k.valid && lane == 0) {
-            a.ivsum[t] = 0u;
+            uint32_t carry = k.carry;
+            if (DELTA) running_sum(v, carry);
+            store_segment(k.p, k.s, lane, v, 0u);
         }
         walker_release();
         h0 = h1;
         h1 = h2;
         h2 = h3;
         c1 = c2;
+    }
+    if (corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
+}
+
+// Delta decoding, value sums in runs: a wave takes kSumsChunk consecutive
+// tasks, and each stretch of them that belongs to one list (every task but
+// the list's last) is a run of consecutive full segments, walked like a
+// single stream (Walker<1>): one descriptor per run, byte offsets chained
+// from segment to segment, the next segment's data in flight while one is
+// summed.  Writes each task's sum of stored differences to ivsum (0 for the
+// last task of a list, whose sum no carry needs).
+constexpr uint32_t kSumsChunk = 8;  // measured: 8 tasks 209 us on C4, 16 213-228, 32 230
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_sums_runs_kernel(
+    BatchArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t total = task_total(a);
+    const uint64_t t0 = ((uint64_t)blockIdx.x * kWaves + wave) * kSumsChunk;
+    if (t0 >= total) return;
+    const uint64_t t_end = t0 + kSumsChunk < total ? t0 + kSumsChunk : total;
+    uint8_t *stage = s_stage + wave * kStageBytes;
+    bool corrupt = false;
+    uint64_t t = t0;
+#pragma unroll 1
+    while (t < t_end) {
+        const TaskHdr h = load_hdr(a, t, t_end);
+        if (h.last) {
+            if (lane == 0) a.ivsum[t] = 0u;
+            ++t;
+            continue;
+        }
+        // the run: tasks t .. u - 1, up to the list's last task (excluded) or the chunk's end
+        const uint64_t segs = (h.p.n + kSegInts - 1) / kSegInts;
+        const uint64_t list_last = t + (segs - 1 - h.s);
+        const uint64_t u = list_last < t_end ? list_last : t_end;
+        Walker<1> w;
+        walker_begin(h.p, w, h.s, h.s + (u - t), h.boff, lane);
+#pragma unroll 1
+        for (uint64_t i = 0; i < u - t; ++i) {
+            SegPlan seg;
+            uint32_t sh16;
+            walker_step(h.p, w, stage, lane, seg, sh16);
+            uint32_t v[4][4];
+            extract_segment(h.p, h.s + i, stage, seg, sh16, lane, v);
+            walker_release();
+            uint32_t x = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) x += v[q][0] + v[q][1] + v[q][2] + v[q][3];
+            x = wave_last(wave_incl_scan(x));
+            if (lane == 0) a.ivsum[t + i] = x;
+        }
+        corrupt |= w.corrupt;
+        t = u;
     }
     if (corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
 }
@@ -461,7 +504,8 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
                                    a);
             break;
         case kBatchItemSums:
-            hipLaunchKernelGGL((batch_walk_kernel<kSums>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL(batch_sums_runs_kernel, dim3(wave_grid((a.t_cap + kSumsChunk - 1) / kSumsChunk)),
+                               dim3(kThreads), 0, s, a);
             break;
         case kBatchWork:
             if (encode) {
