@@ -333,7 +333,8 @@ int do_batch(const BatchCall &c, uint32_t chunk, void *stream) {
                             [&] { return launch_batch(a, kBatchWork, c.encode, delta, s); }));
 }
 
-// Times each chunk choice on the caller's batch and keeps the fastest.
+// Times each chunk choice on the caller's batch (median of five calls after
+// two untimed ones) and keeps the fastest.
 int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -348,8 +349,9 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
     for (uint32_t g : kChunkChoices) {
         for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_batch(c, g, stream);
         if (st != SVB_OK) break;
-        float times[3];
-        for (int r = 0; r < 3 && st == SVB_OK; ++r) {
+        constexpr int kReps = 5;
+        float times[kReps];
+        for (int r = 0; r < kReps && st == SVB_OK; ++r) {
             if (hipEventRecord(e0, s) != hipSuccess) st = SVB_ERR_HIP;
             if (st == SVB_OK) st = do_batch(c, g, stream);
             if (st == SVB_OK && hipEventRecord(e1, s) != hipSuccess) st = SVB_ERR_HIP;
@@ -357,7 +359,8 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
             if (st == SVB_OK && hipEventElapsedTime(&times[r], e0, e1) != hipSuccess) st = SVB_ERR_HIP;
         }
         if (st != SVB_OK) break;
-        const float med = std::max(std::min(times[0], times[1]), std::min(std::max(times[0], times[1]), times[2]));
+        std::sort(times, times + kReps);
+        const float med = times[kReps / 2];
         if (med < best_ms) {
             best_ms = med;
             best = g;
