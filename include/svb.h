@@ -326,10 +326,10 @@ void svb_release_workspace(void);
  * there were (or a negative svb_status).  Kernel names: "group_bytes",
  * "scan_offsets", "group_sums", "scan_sums", "decode", "decode_delta",
  * "encode", "encode_delta", and for the batched calls "batch_count",
- * "batch_scan_lists", "batch_map", "batch_task_bytes", "batch_scan_offsets",
- * "batch_desc", "batch_task_sums", "batch_scan_sums", "batch_carries",
- * "batch_decode", "batch_encode" (a
- * scan of more than 65536 values is three kernels under one name).
+ * "batch_scan_lists", "batch_map" and "batch_task_bytes" (encoding),
+ * "batch_map_bytes" (decoding), "batch_scan_offsets", "batch_task_sums",
+ * "batch_scan_sums", "batch_desc", "batch_decode", "batch_encode" (a scan of
+ * more than 16384 values is three kernels under one name).
  */
 int svb_set_kernel_timing(int enable);
 int svb_kernel_times(const char **names, float *ms, int cap);

@@ -300,16 +300,15 @@ int prepare_batch(const BatchCall &c, uint32_t C, uint64_t T, uint8_t *sc, Batch
              return launch_scan(a.ibytes, a.ioff, T, true, 0u, s, nullptr, scan_scr);
          }))) != SVB_OK)
         return st;
-    if ((st = run("batch_desc", kBatchDesc)) != SVB_OK) return st;
     if (!c.encode && delta) {
         if ((st = run("batch_task_sums", kBatchItemSums)) != SVB_OK) return st;
         if ((st = hip_status(timed("batch_scan_sums", s, [&] {
                  return launch_scan(a.ivsum, a.ivpre, T, false, 0u, s, nullptr, scan_scr);
              }))) != SVB_OK)
             return st;
-        if ((st = run("batch_carries", kBatchCarries)) != SVB_OK) return st;
     }
-    return SVB_OK;
+    // descriptors last: for delta decoding they carry each task's running sum
+    return run("batch_desc", kBatchDesc);
 }
 
 // chunk = 0: the tuned choice for this kind of call.

@@ -15,13 +15,13 @@
 //      takes the byte lengths of its 1024 values), then a scan -> each task's
 //      byte offset in its list's data stream (global scan minus the value at
 //      the list's first task);
-//   4. batch_desc_kernel: one 64-byte descriptor per task (stream, output,
-//      segment, byte offset), so a wave needs a single load to start a task;
-//   5. delta decoding only: batch_sums_runs_kernel sums the stored
+//   4. delta decoding only: batch_sums_runs_kernel sums the stored
 //      differences of every task that is not the last of its list (walking
-//      each list's consecutive tasks as one run), then a scan, and
-//      batch_carry_kernel -> each task's carry in its descriptor (global scan
-//      minus the value at the list's first task, plus the list's start);
+//      each list's consecutive tasks as one run), then a scan;
+//   5. batch_desc_kernel: one 64-byte descriptor per task (stream, output,
+//      segment, byte offset, and for delta decoding the carry: global scan
+//      minus the value at the list's first task, plus the list's start), so a
+//      wave needs a single load to start a task;
 //   6. batch_walk_kernel / batch_encode_kernel: each wave takes a run of
 //      `chunk` consecutive tasks (the tuned parameter).  The decoder keeps a
 //      pipeline three tasks deep: while one segment is decoded from LDS, the
@@ -124,21 +124,13 @@ __global__ __launch_bounds__(kThreads) void batch_desc_kernel(BatchArgs a) {
         d.in = (uint64_t)(a.in8 + a.in_off[i]);
         d.in_bytes = a.in_bytes[i];
         d.out = a.out_off ? (uint64_t)(a.out32 + a.out_off[i]) : 0ull;  // none in a task index
+        if (a.starts) d.carry = a.starts[i] + (a.ivpre[t] - a.ivpre[first]);
     }
     d.n = a.counts[i];
     d.boff = a.ioff[t] - a.ioff[first];
     d.s = (uint32_t)t - first;
     d.word = word;
     a.desc[t] = d;
-}
-
-// Delta decoding: the running sum before each task.
-__global__ __launch_bounds__(kThreads) void batch_carry_kernel(BatchArgs a) {
-    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (t >= task_total(a)) return;
-    const uint32_t first = a.item_first[t];
-    const uint32_t i = a.item_list[t] & ~kLastBit;
-    a.desc[t].carry = a.starts[i] + (a.ivpre[t] - a.ivpre[first]);
 }
 
 // A decode task as a wave sees it (wave-uniform).
@@ -253,8 +245,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
 // Delta decoding, value sums in runs: a wave takes kSumsChunk consecutive
 // tasks, and each stretch of them that belongs to one list (every task but
 // the list's last) is a run of consecutive full segments, walked like a
-// single stream (Walker<1>): one descriptor per run, byte offsets chained
-// from segment to segment, the next segment's data in flight while one is
+// single stream (Walker<1>): the run's list and byte offset are read once
+// (it runs before the descriptors exist), byte offsets are chained from
+// segment to segment, and the next segment's data is in flight while one is
 // summed.  Writes each task's sum of stored differences to ivsum (0 for the
 // last task of a list, whose sum no carry needs).
 constexpr uint32_t kSumsChunk = 8;  // measured: 8 tasks 209 us on C4, 16 213-228, 32 230
@@ -273,25 +266,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     uint64_t t = t0;
 #pragma unroll 1
     while (t < t_end) {
-        const TaskHdr h = load_hdr(a, t, t_end);
-        if (h.last) {
+        const uint32_t word = uniform32(a.item_list[t]);
+        if (word & kLastBit) {
             if (lane == 0) a.ivsum[t] = 0u;
             ++t;
             continue;
         }
+        const uint32_t li = word & ~kLastBit;
+        const uint32_t first = uniform32(a.item_first[t]);
+        DecodeArgs p = {};
+        p.in = a.in8 + uniform64(a.in_off[li]);
+        p.in_bytes = uniform64(a.in_bytes[li]);
+        p.n = uniform64(a.counts[li]);
+        const uint64_t s0 = t - first;
+        const uint64_t boff = uniform64(a.ioff[t]) - uniform64(a.ioff[first]);
         // the run: tasks t .. u - 1, up to the list's last task (excluded) or the chunk's end
-        const uint64_t segs = (h.p.n + kSegInts - 1) / kSegInts;
-        const uint64_t list_last = t + (segs - 1 - h.s);
+        const uint64_t segs = (p.n + kSegInts - 1) / kSegInts;
+        const uint64_t list_last = t + (segs - 1 - s0);
         const uint64_t u = list_last < t_end ? list_last : t_end;
         Walker<1> w;
-        walker_begin(h.p, w, h.s, h.s + (u - t), h.boff, lane);
+        walker_begin(p, w, s0, s0 + (u - t), boff, lane);
 #pragma unroll 1
         for (uint64_t i = 0; i < u - t; ++i) {
             SegPlan seg;
             uint32_t sh16;
-            walker_step(h.p, w, stage, lane, seg, sh16);
+            walker_step(p, w, stage, lane, seg, sh16);
             uint32_t v[4][4];
-            extract_segment(h.p, h.s + i, stage, seg, sh16, lane, v);
+            extract_segment(p, s0 + i, stage, seg, sh16, lane, v);
             walker_release();
             uint32_t x = 0;
 #pragma unroll
@@ -489,9 +490,6 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
                 hipLaunchKernelGGL((batch_desc_kernel<true>), dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
             else
                 hipLaunchKernelGGL((batch_desc_kernel<false>), dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
-            break;
-        case kBatchCarries:
-            hipLaunchKernelGGL(batch_carry_kernel, dim3(list_grid(a.t_cap)), dim3(kThreads), 0, s, a);
             break;
         case kBatchItemBytes:
             if (!encode)

@@ -104,8 +104,7 @@ enum BatchPhase {
     kBatchItemBytes = 2,
     kBatchItemSums = 3,
     kBatchWork = 4,
-    kBatchDesc = 5,     // descriptors from the byte offsets
-    kBatchCarries = 6   // delta decode: carries from the value sums
+    kBatchDesc = 5      // descriptors from the byte offsets (and for delta decoding the value-sum prefixes)
 };
 hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s);
 
