@@ -185,13 +185,23 @@ __global__ __launch_bounds__(kThreads) void seg_max_kernel(SeekArgs a) {
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wave;
     if (t >= a.tasks) return;
     const SegRef r = load_seg(a.desc, t);
-    uint32_t v[4][4];
-    const bool corrupt = decode_seg(r, a.delta, s_stage + wave * kStageBytes, lane, v);
+    const uint64_t rem = r.p.n - r.s * kSegInts;
     uint32_t x = 0;
+    bool corrupt;
+    if (rem <= kSegInts / 4) {
+        uint32_t v[4];
+        corrupt = decode_row(r, (uint32_t)rem, a.delta, s_stage + wave * kStageBytes, lane, v);
+        // positions past the end hold 0 (plain) or the last running value (delta)
 #pragma unroll
-    for (uint32_t k = 0; k < 4; ++k)
+        for (uint32_t j = 0; j < 4; ++j) x = max(x, v[j]);
+    } else {
+        uint32_t v[4][4];
+        corrupt = decode_seg(r, a.delta, s_stage + wave * kStageBytes, lane, v);
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) x = max(x, v[k][j]);  // integers past the end are 0
+        for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) x = max(x, v[k][j]);  // as above
+    }
     x = wave_incl_max(x);
     if (lane == kWave - 1) a.rmax[t] = x;
     if (corrupt && lane == 0) *a.err = SVB_DECODE_CORRUPT;
