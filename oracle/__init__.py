@@ -60,6 +60,9 @@ def lib():
         L.svbref_select.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
                                     ctypes.c_uint64, u32p]
         L.svbref_select.restype = ctypes.c_int
+        L.svbref_append.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint64, ctypes.c_int,
+                                    ctypes.c_uint32, u8p]
+        L.svbref_append.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -147,6 +150,21 @@ def select(stream, n, i, delta=False, start=0):
     if lib().svbref_select(sp, s.size, int(n), int(bool(delta)), int(start) & 0xFFFFFFFF, int(i), vp) != 0:
         raise ValueError("corrupt or truncated Stream VByte stream")
     return int(v[0])
+
+
+def append(stream, n, x, delta=False, prev=0):
+    """The stream of the n integers held in `stream` (its exact bytes) followed by the integers x,
+    built without re-encoding the old ones; the first new difference is taken from `prev`.
+    Returns a uint8 array; raises ValueError if `stream` is not exactly what its control bytes
+    describe."""
+    s, sp = _u8(stream)
+    x, xp = _u32(x)
+    out = np.zeros(max(1, max_compressed_bytes(int(n) + x.size)), dtype=np.uint8)
+    _, op = _u8(out)
+    size = lib().svbref_append(sp, s.size, int(n), xp, x.size, int(bool(delta)), int(prev) & 0xFFFFFFFF, op)
+    if size < 0:
+        raise ValueError("stream size does not match its control bytes")
+    return out[:size].copy()
 
 
 # --- batched: Stream VByte applied to each list on its own -------------------

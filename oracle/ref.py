@@ -102,3 +102,21 @@ def select(stream: bytes, n: int, i: int, delta=False, start=0):
     if not 0 <= i < n:
         raise IndexError("select index past the end of the list")
     return decode(stream, n, delta, start)[i]
+
+
+def append(stream: bytes, n: int, values, delta=False, prev=0) -> bytes:
+    """The stream of the n integers in `stream` followed by `values`, assembled from the old
+    stream's codes and bytes (they are not re-encoded) and the new integers' codes and bytes."""
+    ncontrol = (n + 3) // 4
+    codes = [(stream[i // 4] >> (2 * (i % 4))) & 3 for i in range(n)]
+    old_data = bytes(stream[ncontrol:])
+    if len(old_data) != sum(c + 1 for c in codes):
+        raise ValueError("stream size does not match its control bytes")
+    vals = deltas(values, prev) if delta else list(values)
+    lengths = [byte_length(v) for v in vals]
+    codes += [L - 1 for L in lengths]
+    control = bytearray()
+    for b in range((len(codes) + 3) // 4):
+        fields = codes[4 * b: 4 * b + 4] + [0] * (4 - len(codes[4 * b: 4 * b + 4]))
+        control.append(int("".join(format(c, "02b") for c in reversed(fields)), 2))
+    return bytes(control) + old_data + b"".join(v.to_bytes(L, "little") for v, L in zip(vals, lengths))

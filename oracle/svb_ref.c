@@ -184,3 +184,40 @@ int svbref_select(const uint8_t *in, uint64_t in_bytes, uint64_t n, int delta, u
     *value = prev;
     return 0;
 }
+
+/* Append (the paper's closing remark on appending to a stream without
+ * re-encoding it: the data grow at the end, the control stream grows too):
+ * writes to `out` the stream of the n integers held in `in` followed by the k
+ * integers of x.  The old integers' codes keep their places (their last,
+ * partial control byte takes the first new codes), the new codes follow; the
+ * old data bytes are copied unchanged, the new integers' bytes follow.  With
+ * delta != 0 the new integers are stored as differences, the first from
+ * `prev` (the old stream's last value, or its start when n = 0).  in_bytes is
+ * the old stream's exact size.  Returns the new size, or -1 if the old control
+ * bytes describe more data than in_bytes holds. */
+int64_t svbref_append(const uint8_t *in, uint64_t in_bytes, uint64_t n, const uint32_t *x, uint64_t k, int delta,
+                      uint32_t prev, uint8_t *out)
+{
+    uint64_t c_old = (n + 3) / 4, c_new = (n + k + 3) / 4;
+    if (in_bytes < c_old) return -1;
+    uint64_t d_old = 0;
+    for (uint64_t i = 0; i < n; ++i) d_old += ((in[i / 4] >> (2u * (uint32_t)(i % 4))) & 3u) + 1u;
+    if (c_old + d_old != in_bytes) return -1;
+    for (uint64_t b = 0; b < c_new; ++b) out[b] = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t code = (in[i / 4] >> (2u * (uint32_t)(i % 4))) & 3u;
+        out[i / 4] = (uint8_t)(out[i / 4] | (code << (2u * (uint32_t)(i % 4))));
+    }
+    for (uint64_t b = 0; b < d_old; ++b) out[c_new + b] = in[c_old + b];
+    uint64_t p = c_new + d_old;
+    for (uint64_t j = 0; j < k; ++j) {
+        uint32_t v = delta ? (uint32_t)(x[j] - prev) : x[j];
+        prev = x[j];
+        uint32_t len = svbref_length(v);
+        uint64_t i = n + j;
+        out[i / 4] = (uint8_t)(out[i / 4] | ((len - 1u) << (2u * (uint32_t)(i % 4))));
+        for (uint32_t b = 0; b < len; ++b) out[p + b] = (uint8_t)(v >> (8u * b));
+        p += len;
+    }
+    return (int64_t)p;
+}

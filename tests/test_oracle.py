@@ -358,3 +358,42 @@ def test_seek_truncated_stream_is_corrupt():
         oracle.seek(s[:-5], x.size, int(x[-1]), delta=True)
     with pytest.raises(ValueError):
         oracle.select(s[:-5], x.size, x.size - 1, delta=True)
+
+
+# ---------------------------------------------------------------- append
+
+@pytest.mark.parametrize("delta", [False, True])
+def test_append_equals_encoding_of_the_concatenation(delta):
+    """Appending to a stream gives exactly the stream of the concatenated integers (the encoding is
+    canonical), for every old length mod 4 and with an empty side; the old data bytes come through
+    unchanged at their new offset and the old codes keep their bit positions (the integers already
+    stored are not re-encoded)."""
+    rng = np.random.default_rng(31 + delta)
+    for n in [0, 1, 2, 3, 4, 5, 7, 8, 13, 1023, 1024, 1025]:
+        for k in [0, 1, 2, 3, 4, 5, 9, 300]:
+            a = (rng.integers(0, 1 << 32, size=n, dtype=np.uint64) >> rng.integers(0, 32, size=n).astype(np.uint64)
+                 ).astype(np.uint32)
+            b = (rng.integers(0, 1 << 32, size=k, dtype=np.uint64) >> rng.integers(0, 32, size=k).astype(np.uint64)
+                 ).astype(np.uint32)
+            start = int(rng.integers(0, 1 << 32)) if delta else 0
+            old = oracle.encode(a, delta=delta, start=start)
+            prev = (int(a[-1]) if n else start) if delta else 0
+            got = oracle.append(old, n, b, delta=delta, prev=prev)
+            want = oracle.encode(np.concatenate([a, b]), delta=delta, start=start)
+            np.testing.assert_array_equal(got, want, err_msg="n=%d k=%d" % (n, k))
+            py = ref.append(old.tobytes(), n, [int(v) for v in b], delta=delta, prev=prev)
+            assert py == got.tobytes()
+            c_old, c_new = (n + 3) // 4, (n + k + 3) // 4
+            assert got[c_new:c_new + old.size - c_old].tobytes() == old[c_old:].tobytes()
+            for i in range(n):
+                assert (int(got[i // 4]) >> (2 * (i % 4))) & 3 == (int(old[i // 4]) >> (2 * (i % 4))) & 3
+
+
+def test_append_refuses_a_stream_of_the_wrong_size():
+    """The old stream must be exactly what its control bytes describe (Section 4's layout)."""
+    x = np.arange(1, 50, dtype=np.uint32) * 300
+    s = oracle.encode(x)
+    with pytest.raises(ValueError):
+        oracle.append(s[:-1], x.size, np.array([1], np.uint32))
+    with pytest.raises(ValueError):
+        oracle.append(np.concatenate([s, np.zeros(3, np.uint8)]), x.size, np.array([1], np.uint32))
