@@ -273,6 +273,30 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
                       uint32_t outstanding, double *latency_s, double *wall_s);
 
 /*
+ * Append without re-encoding the stored integers (the paper's closing remark:
+ * data added at the end of a stream, its control stream grown).  svb_append
+ * writes to `out` the stream of the n integers held in `in` followed by the
+ * k integers at `vals` (device uint32, 4-byte aligned): the old codes keep
+ * their bit positions (the last, partial control byte takes the first new
+ * codes), the old data bytes are copied unchanged, and only the new integers
+ * are encoded.  The result is byte-identical to encoding all n + k integers.
+ * svb_delta_append stores the new integers as differences, the first from
+ * `prev` (the old stream's last value, or its start when n = 0); the result
+ * is then the delta stream of all n + k integers from the old stream's start.
+ *   in_bytes   the old stream's exact size (as the encoder reported it);
+ *              below ceil(n/4) is SVB_ERR_INVALID.  A size that does not
+ *              match the control bytes gives a stream that is not valid.
+ *   out        ceil((n+k)/4) + (in_bytes - ceil(n/4)) + 4k bytes at most;
+ *              must not overlap `in` or `vals`.
+ *   out_bytes  device uint64 (may be NULL): the new stream's size.
+ * Uses the encoder's scratch (about 4.3 bytes per new integer).
+ */
+int svb_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint8_t *out,
+               uint64_t *out_bytes, void *stream);
+int svb_delta_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals,
+                     uint32_t prev, uint8_t *out, uint64_t *out_bytes, void *stream);
+
+/*
  * Seek and select on resident compressed lists (Section 5 benchmarks both
  * operations on the compressed stream).  For list L, value x_i is its i-th
  * integer after the running sum from starts[L] when the lists are

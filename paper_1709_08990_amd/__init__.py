@@ -19,7 +19,7 @@ __all__ = [
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
     "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
     "svb_server_set_batching", "svb_seek_index_create", "svb_seek_batch", "svb_select_batch",
-    "svb_seek_index_destroy",
+    "svb_seek_index_destroy", "svb_append", "svb_delta_append",
     "encode", "decode",
     "LIB_PATH",
 ]
@@ -73,6 +73,8 @@ def lib():
             "svb_seek_batch": (i32, [vp, u32, vp, vp, vp, vp, vp, vp]),
             "svb_select_batch": (i32, [vp, u32, vp, vp, vp, vp, vp]),
             "svb_seek_index_destroy": (i32, [vp]),
+            "svb_append": (i32, [u64, vp, u64, u64, vp, vp, vp, vp]),
+            "svb_delta_append": (i32, [u64, vp, u64, u64, vp, u32, vp, vp, vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -291,6 +293,16 @@ def svb_server_set_batching(server, min_lists, max_wait_us):
 
 def svb_server_destroy(server):
     return _check(lib().svb_server_destroy(server), "svb_server_destroy")
+
+
+def svb_append(n, inp, in_bytes, k, vals, out, out_bytes=None, stream=None):
+    return _check(lib().svb_append(int(n), _ptr(inp), int(in_bytes), int(k), _ptr(vals), _ptr(out), _ptr(out_bytes),
+                                   _stream(stream)), "svb_append")
+
+
+def svb_delta_append(n, inp, in_bytes, k, vals, prev, out, out_bytes=None, stream=None):
+    return _check(lib().svb_delta_append(int(n), _ptr(inp), int(in_bytes), int(k), _ptr(vals), int(prev) & 0xFFFFFFFF,
+                                         _ptr(out), _ptr(out_bytes), _stream(stream)), "svb_delta_append")
 
 
 def svb_seek_index_create(m, counts, in_off, in_bytes, inp, starts, total_ints, stream=None):

@@ -185,6 +185,56 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     return hip_status(timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s); }));
 }
 
+// Append without re-encoding the stored integers: the new integers are
+// encoded into scratch by the single-stream encoder, then the result is
+// assembled by byte copies (old control bytes, merged control bytes, old
+// data, new data).
+int do_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint32_t prev,
+              bool delta, uint8_t *out, uint64_t *out_bytes, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n > SVB_MAX_N || k > SVB_MAX_N || n + k > SVB_MAX_N) return SVB_ERR_INVALID;
+    if (out_bytes && !aligned8(out_bytes)) return SVB_ERR_INVALID;
+    const uint64_t c_old = (n + 3) / 4, c_new = (n + k + 3) / 4, c_k = (k + 3) / 4;
+    if (in_bytes < c_old || (in_bytes && !in)) return SVB_ERR_INVALID;
+    if (k && (!vals || !aligned4(vals))) return SVB_ERR_INVALID;
+    if (!out && (in_bytes || k)) return SVB_ERR_INVALID;
+    const uint64_t d_old = in_bytes - c_old;
+    if (k == 0) return hip_status(launch_copy_bytes(in, out, in_bytes, nullptr, 0, out_bytes, 0, s));
+    const uint64_t segs = (k + kSegInts - 1) / kSegInts;
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_tmp = 0, o_sb = up16(c_k + 4 * k), o_so = o_sb + up16(4 * segs), o_size = o_so + up16(8 * segs);
+    const uint64_t o_scan = o_size + 16, need = o_scan + up16(scan_scratch_bytes(segs));
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *w;
+    int st = acquire_locked(s, &w);
+    if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    uint8_t *tmp = sc + o_tmp;
+    uint64_t *tmp_size = (uint64_t *)(sc + o_size);
+    EncodeStream e;
+    e.in = vals;
+    e.n = k;
+    e.out = tmp;
+    e.start = prev;
+    uint32_t *seg_bytes = (uint32_t *)(sc + o_sb);
+    uint64_t *seg_off = (uint64_t *)(sc + o_so);
+    auto ok = [](hipError_t x) { return x == hipSuccess; };
+    if (!ok(timed("encode_sizes", s, [&] { return launch_encode_sizes(e, delta, seg_bytes, segs, s); })) ||
+        !ok(timed("scan_offsets", s, [&] { return launch_scan(seg_bytes, seg_off, segs, true, 0u, s, nullptr, sc + o_scan); })) ||
+        !ok(timed(delta ? "encode_delta" : "encode", s,
+                  [&] { return launch_encode_pack(e, delta, seg_off, segs, tmp_size, s); })) ||
+        !ok(timed("append_copy", s, [&] { return launch_copy_bytes(in, out, n / 4, nullptr, 0, nullptr, 0, s); })) ||
+        !ok(timed("append_ctrl", s, [&] { return launch_merge_ctrl(in, tmp, out, n, k, s); })) ||
+        !ok(timed("append_copy", s,
+                  [&] { return launch_copy_bytes(in + c_old, out + c_new, d_old, nullptr, 0, nullptr, 0, s); })) ||
+        !ok(timed("append_copy", s, [&] {
+            return launch_copy_bytes(tmp + c_k, out + c_new + d_old, 4 * k, tmp_size, c_k, out_bytes, c_new + d_old, s);
+        })))
+        return SVB_ERR_HIP;
+    return SVB_OK;
+}
+
 // ---------------------------------------------------------------- batched calls
 
 // Tasks (segments) per wave of the main pass, per (device, kind); kind = 2 encode + delta.
@@ -481,6 +531,16 @@ int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                      uint64_t total_ints, void *stream) {
     BatchCall c = {true, m, counts, in_off, nullptr, in, out_off, out, out_bytes, starts, total_ints, nullptr};
     return do_batch(c, 0, stream);
+}
+
+int svb_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint8_t *out,
+               uint64_t *out_bytes, void *stream) {
+    return do_append(n, in, in_bytes, k, vals, 0u, false, out, out_bytes, stream);
+}
+
+int svb_delta_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint32_t prev,
+                     uint8_t *out, uint64_t *out_bytes, void *stream) {
+    return do_append(n, in, in_bytes, k, vals, prev, true, out, out_bytes, stream);
 }
 
 int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,

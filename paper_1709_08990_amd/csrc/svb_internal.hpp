@@ -161,6 +161,13 @@ hipError_t launch_encode_sizes(const EncodeStream &e, bool delta, uint32_t *seg_
 hipError_t launch_encode_pack(const EncodeStream &e, bool delta, const uint64_t *seg_off, uint64_t segs,
                               uint64_t *out_bytes, hipStream_t s);
 hipError_t launch_copy(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t s);
+// Append: a byte copy at any alignments (the count is len, or *len_dev -
+// len_sub when len_dev is set, at most len; size_out, if set, receives
+// size_base + the count), and the merged control bytes from floor(n/4) on.
+hipError_t launch_copy_bytes(const uint8_t *src, uint8_t *dst, uint64_t len, const uint64_t *len_dev,
+                             uint64_t len_sub, uint64_t *size_out, uint64_t size_base, hipStream_t s);
+hipError_t launch_merge_ctrl(const uint8_t *old_ctrl, const uint8_t *new_ctrl, uint8_t *out, uint64_t n, uint64_t k,
+                             hipStream_t s);
 hipError_t launch_fill(uint32_t *out, uint64_t n, uint32_t value, hipStream_t s);
 
 }  // namespace svb
