@@ -28,6 +28,9 @@ Prints one JSON line.  Besides the headline it carries:
   seek_select   seek and select over 2^20 lists of 256 running sums (deltas
                 below 2^8 and 2^16), 2^22 queries per call, queries/s and
                 algorithmic GB/s, the oracle's walk timed beside them;
+  append        2^22 document ids appended to the 2^26-id delta stream
+                without re-encoding it, GB/s against HBM, the oracle's
+                append timed beside it;
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
@@ -486,6 +489,43 @@ def measure_seek(svb, torch, np, inputs, steps, warmup, oracle_sample=20_000):
     return out
 
 
+def measure_append(svb, torch, np, inputs, steps, warmup, n=1 << 26, k=1 << 22):
+    """Append without re-encoding: 2^22 document ids appended to the delta stream of the 2^26 before
+    them (the same generator).  Algorithmic bytes of a call: the old stream read, the new values
+    read, the new stream written.  The result is checked against one encode of all the ids; the
+    oracle's append (one host core) is timed beside it, as this section's CPU baseline."""
+    import oracle
+    x, _ = inputs.docids(n + k, seed=21)
+    x_dev = torch.from_numpy(x.view(np.int32)).cuda()
+    old = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
+    osz = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(n, x_dev, old, 0, osz)
+    want = torch.empty(svb.svb_max_compressed_bytes(n + k), dtype=torch.uint8, device="cuda")
+    wsz = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(n + k, x_dev, want, 0, wsz)
+    torch.cuda.synchronize()
+    old_bytes, new_bytes = int(osz.item()), int(wsz.item())
+    out = torch.empty(svb.svb_max_compressed_bytes(n + k), dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    vals = x_dev[n:]
+    prev = int(x[n - 1])
+    call = lambda: svb.svb_delta_append(n, old, old_bytes, k, vals, prev, out, size)
+    wall, kms = timed_steps(svb, torch, call, steps, warmup)
+    ok = int(size.item()) == new_bytes and bool(torch.equal(out[:new_bytes], want[:new_bytes]))
+    ms = 1e3 * wall / steps
+    alg = old_bytes + 4 * k + new_bytes
+    host_old = old[:old_bytes].cpu().numpy().view(np.uint8)
+    t0 = time.perf_counter()
+    oracle.append(host_old, n, x[n:], delta=True, prev=prev)
+    oracle_s = time.perf_counter() - t0
+    del x_dev, old, want, out
+    return {"stored": n, "appended": k, "old_bytes": old_bytes, "new_bytes": new_bytes, "ms_per_call": ms,
+            "alg_bytes": alg, "GBps": gbs(alg, ms), "frac_of_peak": gbs(alg, ms) / HBM_PEAK_GBS, "kernels_ms": kms,
+            "matches_full_encode": ok,
+            "cpu_oracle": {"ms_per_call": 1e3 * oracle_s, "cores": 1, "kind": "oracle",
+                           "sample": "one append of the same streams, host memory"}}
+
+
 def build_pool(svb, torch, np, inputs, m, total, cap, seed):
     """Serving pool: m delta-coded posting lists (rank-size Zipf lengths in [1, cap] summing to
     `total`, sorted sets over [0, 2^31) drawn on the GPU), encoded by the batched encoder and
@@ -663,6 +703,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 200,000-list batched measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-seek", action="store_true", help="skip the seek/select measurement")
+    ap.add_argument("--no-append", action="store_true", help="skip the append measurement")
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -670,11 +711,11 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
                     "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
                     "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append")
     ap.add_argument("--trace-bench-json", default=None,
                     help="bench line printed by the traced command (for --summarize-trace)")
     args = ap.parse_args()
@@ -780,6 +821,13 @@ def main():
         for b, r in rk.items():
             log("seek %s: %.3g queries/s (%.1f%% of HBM peak), select %.3g queries/s"
                 % (b, r["seek"]["queries_per_s"], 100 * r["seek"]["frac_of_peak"], r["select"]["queries_per_s"]))
+    if not args.no_append:
+        log("append: 2^22 document ids appended to a stream of 2^26")
+        ra = measure_append(svb, torch, np, inputs, max(5, args.steps // 2), 2)
+        assert ra["matches_full_encode"], "append mismatch"
+        line["append"] = ra
+        log("append %.4f ms/call, %.0f GB/s (%.1f%% of peak); oracle %.1f ms"
+            % (ra["ms_per_call"], ra["GBps"], 100 * ra["frac_of_peak"], ra["cpu_oracle"]["ms_per_call"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)
