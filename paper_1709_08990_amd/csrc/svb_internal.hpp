@@ -15,7 +15,7 @@ namespace svb {
 constexpr uint32_t kSegInts = 1024;
 constexpr uint32_t kSegCtrl = kSegInts / 4;
 #ifndef SVB_GROUP_SEGS
-#define SVB_GROUP_SEGS 8
+#define SVB_GROUP_SEGS 4  // measured: 4 as fast as 8 or faster (2^28 delta 0.378 vs 0.385-0.413 ms), 16 slower
 #endif
 constexpr uint32_t kGroupSegs = SVB_GROUP_SEGS;
 constexpr uint64_t kGroupInts = (uint64_t)kSegInts * kGroupSegs;

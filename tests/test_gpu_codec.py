@@ -20,7 +20,7 @@ svb = pytest.importorskip("paper_1709_08990_amd")
 BOUNDS = [(0, 1 << 8), (1 << 8, 1 << 16), (1 << 16, 1 << 24), (1 << 24, 1 << 32)]
 TILE = 4096    # integers per encoder tile
 SEG = 1024     # integers per decoder segment (one wave)
-GROUP = 8192   # integers per decoder group (segments walked by one wave)
+GROUP = 4096   # integers per decoder group (segments walked by one wave)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -84,7 +84,8 @@ def check_round_trip(x, delta=False, start=0, tag=""):
 # ------------------------------------------------------------------ sizes spanning tiles
 
 SIZES = [1, 2, 3, 4, 5, 7, 8, 15, 16, 17, 63, 64, 65, 255, 256, 257, SEG - 1, SEG, SEG + 1, TILE - 1, TILE,
-         TILE + 1, 3 * TILE + 5, GROUP - 1, GROUP, GROUP + 1, 3 * GROUP + SEG - 3, 65_537, 250_001]
+         TILE + 1, 3 * TILE + 5, GROUP - 1, GROUP, GROUP + 1, 3 * GROUP + SEG - 3, 8191, 8192, 8193, 65_537,
+         250_001]
 
 
 @pytest.mark.parametrize("n", SIZES)
