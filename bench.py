@@ -31,6 +31,8 @@ Prints one JSON line.  Besides the headline it carries:
   append        2^22 document ids appended to the 2^26-id delta stream
                 without re-encoding it, GB/s against HBM, the oracle's
                 append timed beside it;
+  zero_control  delta decode of 2^28 running sums of deltas below 2^8 with
+                the general decoder and with the zero-control variant;
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
@@ -62,7 +64,7 @@ WORKLOAD = ("delta decode of 2^26 sorted uint32 document ids: gaps Geometric(1/8
 N_HEAD = 1 << 26
 COPY_WORDS = 1 << 26                     # 256 MiB copied by the ceiling / counter-scaling copy
 COUNTERS_FILE = "counters_decode_delta_docids_2p26.md"
-DOMINANT_SYMBOL = "decode_kernel<1>"     # rocprofv3 name fragment of the delta decode pass
+DOMINANT_SYMBOL = "decode_kernel<1, false>"  # rocprofv3 name fragment of the delta decode pass (general variant)
 COPY_SYMBOL = "copy_kernel"
 
 
@@ -489,6 +491,35 @@ def measure_seek(svb, torch, np, inputs, steps, warmup, oracle_sample=20_000):
     return out
 
 
+def measure_zero_control(svb, torch, np, steps, warmup, n=1 << 28):
+    """The zero-control decoder variant against the general one: delta decode of 2^28 running sums of
+    deltas below 2^8 (every control byte 0).  Each variant is set explicitly; the general one is
+    restored afterwards."""
+    rng = np.random.default_rng(41)
+    x = np.cumsum(rng.integers(0, 256, size=n, dtype=np.uint64), dtype=np.uint64).astype(np.uint32)
+    x_dev = torch.from_numpy(x.view(np.int32)).cuda()
+    del x
+    comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(n, x_dev, comp, 0, size)
+    torch.cuda.synchronize()
+    nb = int(size.item())
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = {"n": n, "compressed_bytes": nb}
+    for v in (0, 1):
+        svb.svb_set_decode_variant(True, v)
+        out.zero_()
+        wall, kms = timed_steps(svb, torch, lambda: svb.svb_delta_decode(n, comp, nb, out, 0), steps, warmup)
+        ms = 1e3 * wall / steps
+        res["variant%d" % v] = {"ms_per_call": ms, "uint32_per_s": n / (ms * 1e-3),
+                                "call_frac_of_peak": gbs(nb + 4 * n, ms) / HBM_PEAK_GBS, "kernels_ms": kms,
+                                "round_trip_ok": bool(torch.equal(out, x_dev))}
+    svb.svb_set_decode_variant(True, 0)
+    res["speedup"] = res["variant0"]["ms_per_call"] / res["variant1"]["ms_per_call"]
+    del x_dev, comp, out
+    return res
+
+
 def measure_append(svb, torch, np, inputs, steps, warmup, n=1 << 26, k=1 << 22):
     """Append without re-encoding: 2^22 document ids appended to the delta stream of the 2^26 before
     them (the same generator).  Algorithmic bytes of a call: the old stream read, the new values
@@ -704,6 +735,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-seek", action="store_true", help="skip the seek/select measurement")
     ap.add_argument("--no-append", action="store_true", help="skip the append measurement")
+    ap.add_argument("--no-zero-control", action="store_true", help="skip the zero-control variant measurement")
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -711,11 +743,11 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
                     "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek --no-append")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
                     "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek --no-append")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control")
     ap.add_argument("--trace-bench-json", default=None,
                     help="bench line printed by the traced command (for --summarize-trace)")
     args = ap.parse_args()
@@ -828,6 +860,13 @@ def main():
         line["append"] = ra
         log("append %.4f ms/call, %.0f GB/s (%.1f%% of peak); oracle %.1f ms"
             % (ra["ms_per_call"], ra["GBps"], 100 * ra["frac_of_peak"], ra["cpu_oracle"]["ms_per_call"]))
+    if not args.no_zero_control:
+        log("zero-control variant: 2^28 running sums of deltas below 2^8")
+        rz = measure_zero_control(svb, torch, np, max(5, args.steps // 2), 2)
+        assert rz["variant0"]["round_trip_ok"] and rz["variant1"]["round_trip_ok"], "zero-control decode mismatch"
+        line["zero_control"] = rz
+        log("zero-control variant: general %.4f ms, zero-control %.4f ms (%.2fx)"
+            % (rz["variant0"]["ms_per_call"], rz["variant1"]["ms_per_call"], rz["speedup"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)

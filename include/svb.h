@@ -273,6 +273,23 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
                       uint32_t outstanding, double *latency_s, double *wall_s);
 
 /*
+ * Decoder variants (the paper's decoder special-cases control bytes of
+ * single-byte integers, Section 4).  Variant 0 is the general decoder.
+ * Variant 1 also decodes every row of 64 blocks whose control bytes are all
+ * zero (256 one-byte integers) by widening bytes, which pays only where such
+ * rows are common (small deltas everywhere) and costs a test per row
+ * elsewhere.  svb_autotune_decode times both on the caller's stream (the
+ * arguments of svb_decode / svb_delta_decode; it decodes several times and
+ * synchronises the stream), keeps the faster for later calls of that kind
+ * (plain or delta) on the current device and writes it to *variant;
+ * svb_set_decode_variant sets it directly.  Both variants give identical
+ * output.  The default is 0.
+ */
+int svb_autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, int delta,
+                        uint32_t *err, int *variant, void *stream);
+int svb_set_decode_variant(int delta, int variant);
+
+/*
  * Append without re-encoding the stored integers (the paper's closing remark:
  * data added at the end of a stream, its control stream grown).  svb_append
  * writes to `out` the stream of the n integers held in `in` followed by the

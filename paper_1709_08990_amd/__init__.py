@@ -19,7 +19,7 @@ __all__ = [
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
     "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
     "svb_server_set_batching", "svb_seek_index_create", "svb_seek_batch", "svb_select_batch",
-    "svb_seek_index_destroy", "svb_append", "svb_delta_append",
+    "svb_seek_index_destroy", "svb_append", "svb_delta_append", "svb_autotune_decode", "svb_set_decode_variant",
     "encode", "decode",
     "LIB_PATH",
 ]
@@ -74,6 +74,8 @@ def lib():
             "svb_select_batch": (i32, [vp, u32, vp, vp, vp, vp, vp]),
             "svb_seek_index_destroy": (i32, [vp]),
             "svb_append": (i32, [u64, vp, u64, u64, vp, vp, vp, vp]),
+            "svb_autotune_decode": (i32, [u64, vp, u64, vp, u32, i32, vp, vp, vp]),
+            "svb_set_decode_variant": (i32, [i32, i32]),
             "svb_delta_append": (i32, [u64, vp, u64, u64, vp, u32, vp, vp, vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
@@ -293,6 +295,19 @@ def svb_server_set_batching(server, min_lists, max_wait_us):
 
 def svb_server_destroy(server):
     return _check(lib().svb_server_destroy(server), "svb_server_destroy")
+
+
+def svb_autotune_decode(n, inp, in_bytes, out, start=0, delta=False, err=None, stream=None):
+    """Times the two decoder variants on this stream; keeps and returns the faster (0 or 1)."""
+    v = ctypes.c_int(-1)
+    _check(lib().svb_autotune_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), int(start) & 0xFFFFFFFF,
+                                     int(bool(delta)), _ptr(err), ctypes.addressof(v), _stream(stream)),
+           "svb_autotune_decode")
+    return v.value
+
+
+def svb_set_decode_variant(delta, variant):
+    return _check(lib().svb_set_decode_variant(int(bool(delta)), int(variant)), "svb_set_decode_variant")
 
 
 def svb_append(n, inp, in_bytes, k, vals, out, out_bytes=None, stream=None):

@@ -126,8 +126,19 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
                             [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s); }));
 }
 
+// Decoder variant per (device, delta): true = the zero-control variant.
+std::map<std::pair<int, int>, bool> g_zc;
+
+bool zc_choice(bool delta) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_zc.find(std::make_pair(dev, delta ? 1 : 0));
+    return it != g_zc.end() && it->second;
+}
+
+// zc: -1 = the chosen variant for this kind of call, else 0 / 1.
 int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
-              uint32_t *err, bool delta, void *stream) {
+              uint32_t *err, bool delta, void *stream, int zc_force = -1) {
     hipStream_t s = (hipStream_t)stream;
     if (n > SVB_MAX_N) return SVB_ERR_INVALID;
     if (err && !aligned4(err)) return SVB_ERR_INVALID;
@@ -145,6 +156,7 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     const uint64_t o_scan = o_gvpre + up16(4 * groups);
     const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
     std::lock_guard<std::mutex> lock(g_mu);
+    const bool zc = zc_force < 0 ? zc_choice(delta) : zc_force != 0;
     Workspace *w;
     int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
@@ -176,13 +188,59 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     a.gvpre = (const uint32_t *)(sc + o_gvpre);
     if (delta) {
         // value sum of every group, then start + their exclusive prefix
-        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s); }))) != SVB_OK) return st;
+        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s, zc); }))) != SVB_OK)
+            return st;
         if ((st = hip_status(timed("scan_sums", s, [&] {
                  return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s, nullptr, sc + o_scan);
              }))) != SVB_OK)
             return st;
     }
-    return hip_status(timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s); }));
+    return hip_status(
+        timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc); }));
+}
+
+// Times the two decoder variants on the caller's stream (median of five
+// calls after two untimed ones each) and keeps the faster for this kind of
+// call on the current device.
+int autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, uint32_t *err,
+                    bool delta, int *chosen, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SVB_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SVB_ERR_HIP;
+    }
+    float best_ms[2] = {1e30f, 1e30f};
+    int st = SVB_OK;
+    for (int v = 0; v < 2 && st == SVB_OK; ++v) {
+        for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_decode(n, in, in_bytes, out, start, err, delta, stream, v);
+        constexpr int kReps = 5;
+        float times[kReps];
+        for (int r = 0; r < kReps && st == SVB_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK) st = do_decode(n, in, in_bytes, out, start, err, delta, stream, v);
+            if (st == SVB_OK && hipEventRecord(e1, s) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK && hipEventSynchronize(e1) != hipSuccess) st = SVB_ERR_HIP;
+            if (st == SVB_OK && hipEventElapsedTime(&times[r], e0, e1) != hipSuccess) st = SVB_ERR_HIP;
+        }
+        if (st == SVB_OK) {
+            std::sort(times, times + kReps);
+            best_ms[v] = times[kReps / 2];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SVB_OK) return st;
+    const bool zc = best_ms[1] < best_ms[0];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_zc[std::make_pair(dev, delta ? 1 : 0)] = zc;
+    }
+    if (chosen) *chosen = zc ? 1 : 0;
+    return SVB_OK;
 }
 
 // Append without re-encoding the stored integers: the new integers are
@@ -531,6 +589,20 @@ int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                      uint64_t total_ints, void *stream) {
     BatchCall c = {true, m, counts, in_off, nullptr, in, out_off, out, out_bytes, starts, total_ints, nullptr};
     return do_batch(c, 0, stream);
+}
+
+int svb_autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, int delta,
+                        uint32_t *err, int *variant, void *stream) {
+    return autotune_decode(n, in, in_bytes, out, start, err, delta != 0, variant, stream);
+}
+
+int svb_set_decode_variant(int delta, int variant) {
+    if (variant != 0 && variant != 1) return SVB_ERR_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_zc[std::make_pair(dev, delta ? 1 : 0)] = variant == 1;
+    return SVB_OK;
 }
 
 int svb_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint8_t *out,

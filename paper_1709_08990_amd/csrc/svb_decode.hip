@@ -60,7 +60,9 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 //   kPlain: store the integers.
 //   kDelta: store their running sum (Section 2), continuing from gvpre[group].
 //   kSums:  store nothing; write the group's sum of decoded values to gvsum.
-template <int MODE>
+//   ZC: rows of all-zero control bytes take the widening path of
+//       extract_segment (the zero-control variant).
+template <int MODE, bool ZC>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
         uint32_t sh16;
         walker_step(p, w, stage, lane, seg, sh16);
         uint32_t v[4][4];
-        extract_segment(p, s, stage, seg, sh16, lane, v);
+        extract_segment<ZC>(p, s, stage, seg, sh16, lane, v);
         walker_release();
         if (MODE == kSums) {
             uint32_t t = 0;
@@ -104,14 +106,24 @@ hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s) {
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc) {
     const uint32_t grid = (uint32_t)((a.groups + kWaves - 1) / kWaves);
-    if (mode == kPlain)
-        hipLaunchKernelGGL((decode_kernel<kPlain>), dim3(grid), dim3(kThreads), 0, s, a);
-    else if (mode == kDelta)
-        hipLaunchKernelGGL((decode_kernel<kDelta>), dim3(grid), dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((decode_kernel<kSums>), dim3(grid), dim3(kThreads), 0, s, a);
+    if (mode == kPlain) {
+        if (zc)
+            hipLaunchKernelGGL((decode_kernel<kPlain, true>), dim3(grid), dim3(kThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((decode_kernel<kPlain, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    } else if (mode == kDelta) {
+        if (zc)
+            hipLaunchKernelGGL((decode_kernel<kDelta, true>), dim3(grid), dim3(kThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((decode_kernel<kDelta, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    } else {
+        if (zc)
+            hipLaunchKernelGGL((decode_kernel<kSums, true>), dim3(grid), dim3(kThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((decode_kernel<kSums, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s);
 uint64_t scan_scratch_bytes(uint64_t m);
 hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
                        void *total = nullptr, void *scratch = nullptr);
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s);
+// zc: the zero-control variant (rows of all-zero control bytes widen bytes).
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false);
 
 // Batched calls.  A task is one 1024-integer segment of one list; each wave of
 // the main pass takes `chunk` consecutive tasks.

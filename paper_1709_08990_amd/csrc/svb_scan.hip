@@ -4,7 +4,11 @@
 // Sections 2 and 4, become scans).
 //
 // WIDE: 64-bit sums (byte offsets).  Otherwise sums modulo 2^32 plus `start`
-// (delta carries).  An optional `total` receives the sum of all m values
+// (delta carries).  A wide scan's values are byte counts of at most a few
+// tens of thousands (a group, segment or task), below 2^18, so one
+// workgroup step of at most 16384 of them sums below 2^32: inside a step the
+// wide scan uses the 32-bit wave scan, and only the carry between steps and
+// tiles is 64-bit.  An optional `total` receives the sum of all m values
 // (64-bit, or 32-bit plus start modulo 2^32).
 //
 // Up to kSingleMax (16384) values: one workgroup of 1024 threads.  Above
@@ -84,38 +88,44 @@ __device__ __forceinline__ A block_prefix(A sum, A *s_wtot, A *total) {
     return pre;
 }
 
-// Writes thread `tid`'s 16 outputs (exclusive sums, offset by `carry`).
+// Writes thread `tid`'s 16 outputs: carry + pre + the exclusive sums of x.
+// The running sum inside the thread's 16 values stays 32-bit (for WIDE: the
+// 16 values and pre sum below 2^32, see above); wide outputs go out as
+// 16-byte stores of two 64-bit values.
 template <bool WIDE>
 __device__ __forceinline__ void store16(void *out, uint64_t base, uint64_t m, uint32_t tid, acc_t<WIDE> carry,
-                                        const uint32_t (&x)[kScanPer]) {
+                                        uint32_t pre, const uint32_t (&x)[kScanPer]) {
     const uint64_t i0 = base + (uint64_t)tid * kScanPer;
-    acc_t<WIDE> y[kScanPer];
-    acc_t<WIDE> run = carry;
+    uint32_t r[kScanPer];
+    uint32_t run = WIDE ? pre : (uint32_t)carry + pre;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) {
-        y[j] = run;
+        r[j] = run;
         run += x[j];
     }
-    if (i0 + kScanPer <= m) {
-        if (WIDE) {
-            uint64_t *o = (uint64_t *)out + i0;
+    if (WIDE) {
+        const uint64_t c = (uint64_t)carry;
+        uint64_t *o = (uint64_t *)out + i0;
+        if (i0 + kScanPer <= m) {
 #pragma unroll
-            for (uint32_t j = 0; j < kScanPer; ++j) o[j] = y[j];
+            for (uint32_t j = 0; j < kScanPer; j += 2) {
+                const uint64_t y0 = c + r[j], y1 = c + r[j + 1];
+                *(u32x4 *)(o + j) = u32x4{(uint32_t)y0, (uint32_t)(y0 >> 32), (uint32_t)y1, (uint32_t)(y1 >> 32)};
+            }
         } else {
-            uint32_t *o = (uint32_t *)out + i0;
 #pragma unroll
-            for (uint32_t j = 0; j < kScanPer; j += 4)
-                *(u32x4 *)(o + j) = u32x4{(uint32_t)y[j], (uint32_t)y[j + 1], (uint32_t)y[j + 2], (uint32_t)y[j + 3]};
+            for (uint32_t j = 0; j < kScanPer; ++j)
+                if (i0 + j < m) o[j] = c + r[j];
         }
     } else {
+        uint32_t *o = (uint32_t *)out + i0;
+        if (i0 + kScanPer <= m) {
 #pragma unroll
-        for (uint32_t j = 0; j < kScanPer; ++j) {
-            if (i0 + j < m) {
-                if (WIDE)
-                    ((uint64_t *)out)[i0 + j] = y[j];
-                else
-                    ((uint32_t *)out)[i0 + j] = (uint32_t)y[j];
-            }
+            for (uint32_t j = 0; j < kScanPer; j += 4) *(u32x4 *)(o + j) = u32x4{r[j], r[j + 1], r[j + 2], r[j + 3]};
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < kScanPer; ++j)
+                if (i0 + j < m) o[j] = r[j];
         }
     }
 }
@@ -135,19 +145,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_
                                                                    uint32_t start, void *total) {
     typedef acc_t<WIDE> A;
     constexpr uint32_t W = kScanThreads / kWave;
-    __shared__ A s_wtot[W + 1];
+    __shared__ uint32_t s_wtot[W + 1];
     const uint32_t tid = threadIdx.x;
     A carry = WIDE ? (A)0 : (A)start;
     for (uint64_t base = 0; base < m; base += kScanTile) {
         uint32_t x[kScanPer];
         load16(in, base, m, tid, x);
-        A sum = 0;
+        uint32_t sum = 0;
 #pragma unroll
         for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
-        A step_total;
-        const A pre = block_prefix<W, A>(sum, s_wtot, &step_total);
-        store16<WIDE>(out, base, m, tid, carry + pre, x);
-        carry += step_total;
+        uint32_t step_total;
+        const uint32_t pre = block_prefix<W, uint32_t>(sum, s_wtot, &step_total);
+        store16<WIDE>(out, base, m, tid, carry, pre, x);
+        carry += (A)step_total;
     }
     if (tid == 0) write_total<WIDE>(total, carry);
 }
@@ -155,17 +165,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(const uint32_
 // Tile t's sum into sums[t] (64-bit for WIDE).
 template <bool WIDE>
 __global__ __launch_bounds__(kTileThreads) void scan_tile_sums_kernel(const uint32_t *in, uint64_t m, uint32_t *sums) {
-    typedef acc_t<WIDE> A;
     constexpr uint32_t W = kTileThreads / kWave;
-    __shared__ A s_wtot[W + 1];
+    __shared__ uint32_t s_wtot[W + 1];
     const uint64_t base = (uint64_t)blockIdx.x * kTileVals;
     uint32_t x[kScanPer];
     load16(in, base, m, threadIdx.x, x);
-    A sum = 0;
+    uint32_t sum = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
-    A tot;
-    (void)block_prefix<W, A>(sum, s_wtot, &tot);
+    uint32_t tot;
+    (void)block_prefix<W, uint32_t>(sum, s_wtot, &tot);
     if (threadIdx.x == 0) {
         if (WIDE) {
             // split into two 32-bit words so the tile sums scan as u32 pairs below
@@ -204,16 +213,16 @@ __global__ __launch_bounds__(kTileThreads) void scan_tile_final_kernel(const uin
                                                                        const uint64_t *pre) {
     typedef acc_t<WIDE> A;
     constexpr uint32_t W = kTileThreads / kWave;
-    __shared__ A s_wtot[W + 1];
+    __shared__ uint32_t s_wtot[W + 1];
     const uint64_t base = (uint64_t)blockIdx.x * kTileVals;
     uint32_t x[kScanPer];
     load16(in, base, m, threadIdx.x, x);
-    A sum = 0;
+    uint32_t sum = 0;
 #pragma unroll
     for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
-    A tot;
-    const A p = block_prefix<W, A>(sum, s_wtot, &tot);
-    store16<WIDE>(out, base, m, threadIdx.x, (A)pre[blockIdx.x] + p, x);
+    uint32_t tot;
+    const uint32_t p = block_prefix<W, uint32_t>(sum, s_wtot, &tot);
+    store16<WIDE>(out, base, m, threadIdx.x, (A)pre[blockIdx.x], p, x);
 }
 
 }  // namespace

@@ -226,11 +226,27 @@ __device__ __forceinline__ void walker_release() {
 // which falls by y_j per integer, the 4 bytes ending at the integer's last
 // byte start at R_j + 4 (j + 1); they are cut out of the aligned 8 bytes
 // around them, and their top L_j bytes are the integer.
+//
+// ZC (the zero-control variant): a row whose 64 control bytes are all zero
+// holds 256 one-byte integers, so a lane's block is the 4 bytes at its offset:
+// one aligned 8-byte read, one funnel shift, byte extracts (Section 4's
+// decoder also special-cases blocks of single-byte integers).  Worth it only
+// where such rows are common, so it is a separate kernel variant.
+template <bool ZC = false>
 __device__ __forceinline__ void extract_segment(const DecodeArgs &p, uint64_t s, const uint8_t *stage,
                                                 const SegPlan &seg, uint32_t sh16, uint32_t lane,
                                                 uint32_t (&v)[4][4]) {
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
+        if (ZC && __ballot(seg.sc.c[k] != 0u) == 0ull) {
+            const uint32_t b = kStagePad + sh16 + seg.off[k];
+            const uint32_t a = b & ~3u;
+            const uint32_t w = __builtin_amdgcn_alignbyte(*(const uint32_t *)(stage + a + 4),
+                                                          *(const uint32_t *)(stage + a), b & 3u);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) v[k][j] = (w >> (8 * j)) & 0xFFu;
+            continue;
+        }
         uint32_t R = kStagePad - 4 + sh16 + seg.off[k];
         const uint32_t nc = ~seg.sc.c[k];
 #pragma unroll
