@@ -8,7 +8,9 @@ other.  The C part is compiled with gcc into ``oracle/libsvbref.so``.
 Every function here follows the plain definition of the format (Section 3,
 Section 4 and Fig. 3 of the paper), of differential coding (Section 2), and of
 the two operations on compressed lists benchmarked in Section 5 (seek: the
-first position whose value reaches a target; select: the value at a position).
+first position whose value reaches a target; select: the value at a position),
+and of the two comparison formats of Table 1 (VByte, Section 1; varint-GB,
+Section 3 and Fig. 1).
 """
 import ctypes
 import os
@@ -63,6 +65,14 @@ def lib():
         L.svbref_append.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint64, ctypes.c_int,
                                     ctypes.c_uint32, u8p]
         L.svbref_append.restype = ctypes.c_int64
+        L.vbref_length.argtypes = [ctypes.c_uint32]
+        L.vbref_length.restype = ctypes.c_uint32
+        for name in ("vbref_encode", "gbref_encode"):
+            getattr(L, name).argtypes = [u32p, ctypes.c_uint64, u8p]
+            getattr(L, name).restype = ctypes.c_uint64
+        for name in ("vbref_decode", "gbref_decode"):
+            getattr(L, name).argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, u32p]
+            getattr(L, name).restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -184,3 +194,59 @@ def decode_lists(streams, counts, delta=False, starts=None):
         st = 0 if starts is None else int(starts[i])
         out.append(decode(s, int(n), delta=delta, start=st)[0])
     return out
+
+
+# ------------------------------------------------------------------ comparison formats (Table 1; VByte Section 1, varint-GB Section 3)
+
+def vbyte_length(v):
+    """VByte bytes of v: the smallest L >= 1 with v < 2^(7L) (1..5)."""
+    return int(lib().vbref_length(int(v) & 0xFFFFFFFF))
+
+
+def vbyte_max_bytes(n):
+    return 5 * n
+
+
+def vbyte_encode(x):
+    """VByte stream of a uint32 array (7 bits per byte, least significant first, top bit 1 = more
+    bytes follow); uint8 numpy array of exact size."""
+    x, xp = _u32(x)
+    out = np.zeros(max(1, vbyte_max_bytes(x.size)), dtype=np.uint8)
+    _, op = _u8(out)
+    size = lib().vbref_encode(xp, x.size, op)
+    return out[:size].copy()
+
+
+def vbyte_decode(stream, n):
+    """(values, bytes_consumed); ValueError if an integer runs past the stream or takes more than 5 bytes."""
+    s, sp = _u8(stream)
+    out = np.zeros(max(1, n), dtype=np.uint32)
+    _, op = _u32(out)
+    used = lib().vbref_decode(sp, s.size, n, op)
+    if used < 0:
+        raise ValueError("corrupt or truncated VByte stream")
+    return out[:n].copy(), int(used)
+
+
+def varintgb_max_bytes(n):
+    return max_compressed_bytes(n)
+
+
+def varintgb_encode(x):
+    """varint-GB stream of a uint32 array (per block of four: control byte, then the data bytes)."""
+    x, xp = _u32(x)
+    out = np.zeros(max(1, varintgb_max_bytes(x.size)), dtype=np.uint8)
+    _, op = _u8(out)
+    size = lib().gbref_encode(xp, x.size, op)
+    return out[:size].copy()
+
+
+def varintgb_decode(stream, n):
+    """(values, bytes_consumed); ValueError if a block runs past the stream."""
+    s, sp = _u8(stream)
+    out = np.zeros(max(1, n), dtype=np.uint32)
+    _, op = _u32(out)
+    used = lib().gbref_decode(sp, s.size, n, op)
+    if used < 0:
+        raise ValueError("corrupt or truncated varint-GB stream")
+    return out[:n].copy(), int(used)

@@ -221,3 +221,108 @@ int64_t svbref_append(const uint8_t *in, uint64_t in_bytes, uint64_t n, const ui
     }
     return (int64_t)p;
 }
+
+/* ------------------------------------------------------------------------
+ * The two byte-oriented comparison formats of Table 1.
+ *
+ * VByte (Section 1): an integer is written from its least significant bits
+ * up, seven bits per byte; the top bit of a byte says whether another byte of
+ * the same integer follows.  The paper's examples (32 is the single byte
+ * 0x20, 128 is 0x80 then 0x01) fix the flag: 1 = more bytes follow, 0 = last
+ * byte.  A 32-bit integer takes 1 to 5 bytes.
+ *
+ * varint-GB (Section 3, Fig. 1): blocks of four integers, each a control
+ * byte (the four 2-bit codes, integer j of the block in bits 2j..2j+1, code =
+ * length - 1) followed by the four integers' little-endian data bytes.  A last block with
+ * fewer than four integers holds only their data bytes, its unused codes 0;
+ * n is kept out of band.
+ * ------------------------------------------------------------------------ */
+
+/* VByte length of v: the smallest L >= 1 with v < 2^(7L), as the chain of
+ * comparisons it is. */
+uint32_t vbref_length(uint32_t v)
+{
+    if (v < (1u << 7)) return 1;
+    if (v < (1u << 14)) return 2;
+    if (v < (1u << 21)) return 3;
+    if (v < (1u << 28)) return 4;
+    return 5;
+}
+
+/* VByte encoding of x[0..n); returns the bytes written. */
+uint64_t vbref_encode(const uint32_t *x, uint64_t n, uint8_t *out)
+{
+    uint64_t p = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t v = x[i];
+        while (v >= 128u) {
+            out[p++] = (uint8_t)(0x80u | (v & 0x7Fu));
+            v >>= 7;
+        }
+        out[p++] = (uint8_t)v;
+    }
+    return p;
+}
+
+/* Decodes n integers from in[0..in_bytes): each integer's bytes are read
+ * until one with the top bit clear; value = sum of (byte & 0x7F) * 2^(7k)
+ * modulo 2^32.  Returns the bytes consumed, or -1 if an integer runs past
+ * in_bytes or takes more than five bytes (no 32-bit integer needs more).
+ * Bytes after the n-th integer are not read. */
+int64_t vbref_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t *out)
+{
+    uint64_t p = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t v = 0;
+        uint32_t k = 0;
+        for (;;) {
+            if (p >= in_bytes || k == 5) return -1;
+            uint8_t b = in[p++];
+            v |= (uint32_t)(b & 0x7Fu) << (7u * k);
+            ++k;
+            if ((b & 0x80u) == 0) break;
+        }
+        out[i] = v;
+    }
+    return (int64_t)p;
+}
+
+/* varint-GB encoding of x[0..n); returns the bytes written. */
+uint64_t gbref_encode(const uint32_t *x, uint64_t n, uint8_t *out)
+{
+    uint64_t p = 0;
+    for (uint64_t b = 0; b * 4 < n; ++b) {
+        uint64_t ctrl_at = p++;
+        uint8_t ctrl = 0;
+        for (uint32_t j = 0; j < 4 && b * 4 + j < n; ++j) {
+            uint32_t v = x[b * 4 + j];
+            uint32_t len = svbref_length(v);
+            ctrl = (uint8_t)(ctrl | ((len - 1u) << (2u * j)));
+            for (uint32_t k = 0; k < len; ++k) out[p++] = (uint8_t)(v >> (8u * k));
+        }
+        out[ctrl_at] = ctrl;
+    }
+    return p;
+}
+
+/* Decodes n integers from a varint-GB stream: a control byte, then the data
+ * bytes of the block's (up to four) integers.  Returns the bytes consumed, or
+ * -1 if a block runs past in_bytes.  The codes of absent integers in a last
+ * partial block are ignored. */
+int64_t gbref_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t *out)
+{
+    uint64_t p = 0;
+    for (uint64_t b = 0; b * 4 < n; ++b) {
+        if (p >= in_bytes) return -1;
+        uint8_t ctrl = in[p++];
+        for (uint32_t j = 0; j < 4 && b * 4 + j < n; ++j) {
+            uint32_t len = ((ctrl >> (2u * j)) & 3u) + 1u;
+            if (p + len > in_bytes) return -1;
+            uint32_t v = 0;
+            for (uint32_t k = 0; k < len; ++k) v |= (uint32_t)in[p + k] << (8u * k);
+            p += len;
+            out[b * 4 + j] = v;
+        }
+    }
+    return (int64_t)p;
+}

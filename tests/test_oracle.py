@@ -397,3 +397,103 @@ def test_append_refuses_a_stream_of_the_wrong_size():
         oracle.append(s[:-1], x.size, np.array([1], np.uint32))
     with pytest.raises(ValueError):
         oracle.append(np.concatenate([s, np.zeros(3, np.uint8)]), x.size, np.array([1], np.uint32))
+
+
+# ---------------------------------------------------------------- comparison formats (Table 1)
+
+VB_BOUNDS = [0, 1, 127, 128, (1 << 14) - 1, 1 << 14, (1 << 21) - 1, 1 << 21, (1 << 28) - 1, 1 << 28,
+             0xFFFFFFFF]
+
+
+def test_vbyte_paper_examples(golden_dir):
+    """Section 1: 32 is one byte, 128 is 0x80 0x01 (top bit 1 = another byte follows)."""
+    with open(os.path.join(golden_dir, "vbyte_examples.json")) as f:
+        g = json.load(f)
+    for ex in g["examples"]:
+        s = oracle.vbyte_encode(np.array([ex["value"]], dtype=np.uint32))
+        assert list(s) == ex["bytes"]
+        vals, used = oracle.vbyte_decode(s, 1)
+        assert int(vals[0]) == ex["value"] and used == len(ex["bytes"])
+
+
+def test_vbyte_lengths_at_every_boundary():
+    """Seven bits per byte: v takes ceil(bits(v) / 7) bytes, at least 1; checked at each power
+    of 2^7 and on a random sample against that count."""
+    rng = np.random.default_rng(5)
+    vals = VB_BOUNDS + [int(v) for v in rng.integers(0, 1 << 32, size=2000, dtype=np.uint64) >>
+                        rng.integers(0, 32, size=2000).astype(np.uint64)]
+    for v in vals:
+        want = max(1, -(-int(v).bit_length() // 7))
+        assert oracle.vbyte_length(v) == want, v
+        assert oracle.vbyte_encode(np.array([v], dtype=np.uint32)).size == want
+
+
+def test_vbyte_bytes_are_seven_bit_digits():
+    """Every byte but the last has the top bit set; the low seven bits are the base-128 digits of
+    the value, least significant first."""
+    for v in VB_BOUNDS + [300, 0x12345678]:
+        s = [int(b) for b in oracle.vbyte_encode(np.array([v], dtype=np.uint32))]
+        assert all(b & 0x80 for b in s[:-1]) and not s[-1] & 0x80
+        assert sum((b & 0x7F) << (7 * k) for k, b in enumerate(s)) == v
+
+
+def test_vbyte_round_trip_and_errors():
+    rng = np.random.default_rng(6)
+    for n in (0, 1, 2, 5, 1000):
+        x = (rng.integers(0, 1 << 32, size=n, dtype=np.uint64) >> rng.integers(0, 32, size=n).astype(np.uint64)
+             ).astype(np.uint32)
+        s = oracle.vbyte_encode(x)
+        got, used = oracle.vbyte_decode(s, n)
+        assert np.array_equal(got, x) and used == s.size
+        assert s.size == sum(oracle.vbyte_length(int(v)) for v in x)
+        if n:
+            with pytest.raises(ValueError):
+                oracle.vbyte_decode(s[:-1], n)
+    with pytest.raises(ValueError):  # six bytes for one integer
+        oracle.vbyte_decode(np.array([0x80] * 5 + [0], dtype=np.uint8), 1)
+    # a non-minimal but valid encoding (0 in two bytes) decodes; bits past 2^32 drop
+    assert oracle.vbyte_decode(np.array([0x80, 0x00], dtype=np.uint8), 1)[0][0] == 0
+    assert oracle.vbyte_decode(np.array([0xFF] * 4 + [0x7F], dtype=np.uint8), 1)[0][0] == 0xFFFFFFFF
+
+
+def test_varintgb_fig1_blocks(golden_dir):
+    """Fig. 1a/1b: the blocks take 9 and 6 bytes; control byte first, then the data bytes
+    (codes least significant first, data little-endian, as for Stream VByte)."""
+    with open(os.path.join(golden_dir, "fig1_varint_gb_blocks.json")) as f:
+        g = json.load(f)
+    for blk in g["blocks"]:
+        x = np.array(blk["values"], dtype=np.uint32)
+        s = oracle.varintgb_encode(x)
+        assert s.size == blk["total_bytes"]
+        assert [(int(s[0]) >> (2 * j)) & 3 for j in range(4)] == [L - 1 for L in blk["lengths"]]
+        data, p = [], 1
+        for L in blk["lengths"]:
+            data.append(sum(int(s[p + k]) << (8 * k) for k in range(L)))
+            p += L
+        assert data == blk["values"]
+        vals, used = oracle.varintgb_decode(s, 4)
+        assert list(vals) == blk["values"] and used == blk["total_bytes"]
+
+
+def test_varintgb_is_stream_vbyte_interleaved():
+    """Same control bytes and data bytes as Stream VByte (Section 4 separates them): block b of
+    varint-GB is control byte b followed by that block's data bytes."""
+    rng = np.random.default_rng(7)
+    for n in (1, 3, 4, 5, 63, 64, 65, 1001):
+        x = (rng.integers(0, 1 << 32, size=n, dtype=np.uint64) >> rng.integers(0, 32, size=n).astype(np.uint64)
+             ).astype(np.uint32)
+        svb_s = oracle.encode(x)
+        nc = (n + 3) // 4
+        ctrl, data = svb_s[:nc], svb_s[nc:]
+        want, p = [], 0
+        for b in range(nc):
+            want.append(int(ctrl[b]))
+            nb = sum(((int(ctrl[b]) >> (2 * j)) & 3) + 1 for j in range(min(4, n - 4 * b)))
+            want.extend(int(v) for v in data[p:p + nb])
+            p += nb
+        gb = oracle.varintgb_encode(x)
+        assert list(gb) == want
+        got, used = oracle.varintgb_decode(gb, n)
+        assert np.array_equal(got, x) and used == gb.size == svb_s.size
+        with pytest.raises(ValueError):
+            oracle.varintgb_decode(gb[:-1], n)
