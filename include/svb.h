@@ -314,6 +314,45 @@ int svb_delta_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t 
                      uint32_t prev, uint8_t *out, uint64_t *out_bytes, void *stream);
 
 /*
+ * The two comparison formats of Table 1, for measuring Stream VByte against
+ * them on the same data (Section 5 compares speed and size).
+ *
+ * VByte (Section 1): each integer in 1 to 5 bytes of seven data bits, least
+ * significant first; a byte's top bit is 1 when another byte of the same
+ * integer follows (the paper's examples: 32 -> 0x20, 128 -> 0x80 0x01).
+ * varint-GB (Section 3, Fig. 1): per block of four integers, a control byte
+ * (integer j of the block in bits 2j..2j+1, code = byte length - 1) followed
+ * by the block's little-endian data bytes; a last block of fewer than four
+ * integers holds only their bytes (its unused codes 0).  n is kept out of
+ * band for both.
+ *
+ * Encoders: `in` device uint32 (4-byte aligned); `out` at least
+ * svb_vbyte_max_bytes(n) / svb_varintgb_max_bytes(n) bytes, any alignment;
+ * out_bytes device uint64 (may be NULL) receives the stream's size.  The
+ * encoding is unique (minimal lengths), so streams compare byte for byte.
+ *
+ * Decoders: in_bytes may exceed the stream (later bytes are not used); below
+ * n (VByte) or n + ceil(n/4) (varint-GB) it is SVB_ERR_INVALID.  `out`
+ * device uint32, 4-byte aligned, n values.  *err (device uint32, may be
+ * NULL) is set to SVB_DECODE_CORRUPT when the stream ends before the n-th
+ * integer, or (VByte) one of the first n integers takes more than 5 bytes;
+ * the output is then unspecified and nothing outside it is written.  VByte
+ * decodes in three passes (integer ends per 1 KiB tile, a scan, the decode);
+ * varint-GB, whose block positions form a chain through the control bytes,
+ * in five (chunk maps of the chain from each of the 17 possible entry offsets,
+ * their composition over 8 KiB tiles and 512 KiB supertiles, the true chain,
+ * the decode).  Scratch: VByte 12 bytes per KiB of stream; varint-GB about
+ * 280 bytes per KiB.
+ */
+uint64_t svb_vbyte_max_bytes(uint64_t n);
+int svb_vbyte_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, void *stream);
+int svb_vbyte_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err, void *stream);
+uint64_t svb_varintgb_max_bytes(uint64_t n);
+int svb_varintgb_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, void *stream);
+int svb_varintgb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err,
+                        void *stream);
+
+/*
  * Seek and select on resident compressed lists (Section 5 benchmarks both
  * operations on the compressed stream).  For list L, value x_i is its i-th
  * integer after the running sum from starts[L] when the lists are
@@ -369,8 +408,11 @@ void svb_release_workspace(void);
  * "encode", "encode_delta", and for the batched calls "batch_count",
  * "batch_scan_lists", "batch_map" and "batch_task_bytes" (encoding),
  * "batch_map_bytes" (decoding), "batch_scan_offsets", "batch_task_sums",
- * "batch_scan_sums", "batch_desc", "batch_decode", "batch_encode" (a scan of
- * more than 16384 values is three kernels under one name).
+ * "batch_scan_sums", "batch_desc", "batch_decode", "batch_encode", for the
+ * comparison formats "cmp_sizes", "vbyte_encode", "varintgb_encode",
+ * "vbyte_ends", "vbyte_decode", "varintgb_maps", "varintgb_super",
+ * "varintgb_top", "varintgb_tiles", "varintgb_decode" (a scan of more than
+ * 16384 values is three kernels under one name).
  */
 int svb_set_kernel_timing(int enable);
 int svb_kernel_times(const char **names, float *ms, int cap);

@@ -77,6 +77,12 @@ def lib():
             "svb_autotune_decode": (i32, [u64, vp, u64, vp, u32, i32, vp, vp, vp]),
             "svb_set_decode_variant": (i32, [i32, i32]),
             "svb_delta_append": (i32, [u64, vp, u64, u64, vp, u32, vp, vp, vp]),
+            "svb_vbyte_max_bytes": (u64, [u64]),
+            "svb_vbyte_encode": (i32, [u64, vp, vp, vp, vp]),
+            "svb_vbyte_decode": (i32, [u64, vp, u64, vp, vp, vp]),
+            "svb_varintgb_max_bytes": (u64, [u64]),
+            "svb_varintgb_encode": (i32, [u64, vp, vp, vp, vp]),
+            "svb_varintgb_decode": (i32, [u64, vp, u64, vp, vp, vp]),
             "svb_strerror": (ctypes.c_char_p, [i32]),
             "svb_release_workspace": (None, []),
             "svb_version": (ctypes.c_char_p, []),
@@ -318,6 +324,34 @@ def svb_append(n, inp, in_bytes, k, vals, out, out_bytes=None, stream=None):
 def svb_delta_append(n, inp, in_bytes, k, vals, prev, out, out_bytes=None, stream=None):
     return _check(lib().svb_delta_append(int(n), _ptr(inp), int(in_bytes), int(k), _ptr(vals), int(prev) & 0xFFFFFFFF,
                                          _ptr(out), _ptr(out_bytes), _stream(stream)), "svb_delta_append")
+
+
+def svb_vbyte_max_bytes(n):
+    return int(lib().svb_vbyte_max_bytes(int(n)))
+
+
+def svb_vbyte_encode(n, inp, out, out_bytes=None, stream=None):
+    return _check(lib().svb_vbyte_encode(int(n), _ptr(inp), _ptr(out), _ptr(out_bytes), _stream(stream)),
+                  "svb_vbyte_encode")
+
+
+def svb_vbyte_decode(n, inp, in_bytes, out, err=None, stream=None):
+    return _check(lib().svb_vbyte_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), _ptr(err), _stream(stream)),
+                  "svb_vbyte_decode")
+
+
+def svb_varintgb_max_bytes(n):
+    return int(lib().svb_varintgb_max_bytes(int(n)))
+
+
+def svb_varintgb_encode(n, inp, out, out_bytes=None, stream=None):
+    return _check(lib().svb_varintgb_encode(int(n), _ptr(inp), _ptr(out), _ptr(out_bytes), _stream(stream)),
+                  "svb_varintgb_encode")
+
+
+def svb_varintgb_decode(n, inp, in_bytes, out, err=None, stream=None):
+    return _check(lib().svb_varintgb_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), _ptr(err), _stream(stream)),
+                  "svb_varintgb_decode")
 
 
 def svb_seek_index_create(m, counts, in_off, in_bytes, inp, starts, total_ints, stream=None):

@@ -556,6 +556,127 @@ int serve_walk(BatchArgs &a, bool delta, hipStream_t s) {
     return hip_status(launch_batch(a, kBatchWork, false, delta, s));
 }
 
+// The comparison formats (Table 1).  Encoding: bytes per segment, a scan,
+// the pack.
+int do_cmp_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, int fmt, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n > SVB_MAX_N) return SVB_ERR_INVALID;
+    if (out_bytes && !aligned8(out_bytes)) return SVB_ERR_INVALID;
+    if (n == 0) return zero_u64(out_bytes, s);
+    if (!in || !out || !aligned4(in)) return SVB_ERR_INVALID;
+    const uint64_t segs = (n + kSegInts - 1) / kSegInts;
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_bytes = 0, o_off = up16(4 * segs), o_scan = o_off + up16(8 * segs);
+    const uint64_t need = o_scan + up16(scan_scratch_bytes(segs));
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *w;
+    int st = acquire_locked(s, &w);
+    if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    CmpEncodeArgs a;
+    a.in = in;
+    a.n = n;
+    a.out = out;
+    a.seg_bytes = (uint32_t *)(sc + o_bytes);
+    a.seg_off = (const uint64_t *)(sc + o_off);
+    a.segs = segs;
+    a.out_bytes = out_bytes;
+    const char *name = fmt == kFmtVByte ? "vbyte_encode" : "varintgb_encode";
+    if ((st = hip_status(timed("cmp_sizes", s, [&] { return launch_cmp_encode(a, fmt, true, s); }))) != SVB_OK)
+        return st;
+    if ((st = hip_status(timed("scan_offsets", s, [&] {
+             return launch_scan(a.seg_bytes, sc + o_off, segs, true, 0u, s, nullptr, sc + o_scan);
+         }))) != SVB_OK)
+        return st;
+    return hip_status(timed(name, s, [&] { return launch_cmp_encode(a, fmt, false, s); }));
+}
+
+// VByte decoding: integer ends per tile, a scan of them, the decode pass.
+int do_vb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n > SVB_MAX_N) return SVB_ERR_INVALID;
+    if (err && !aligned4(err)) return SVB_ERR_INVALID;
+    if (n == 0) return SVB_OK;
+    if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
+    if (in_bytes < n) return SVB_ERR_INVALID;
+    const uint64_t tiles = vb_tiles(in_bytes);
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_cnt = 0, o_off = up16(4 * tiles), o_tot = o_off + up16(8 * tiles), o_scan = o_tot + 16;
+    const uint64_t need = o_scan + up16(scan_scratch_bytes(tiles));
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *w;
+    int st = acquire_locked(s, &w);
+    if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    VbDecodeArgs a;
+    a.in = in;
+    a.in_bytes = in_bytes;
+    a.n = n;
+    a.tiles = tiles;
+    a.tcount = (uint32_t *)(sc + o_cnt);
+    a.toff = (const uint64_t *)(sc + o_off);
+    a.total = (const uint64_t *)(sc + o_tot);
+    a.out = out;
+    a.err = err;
+    if ((st = hip_status(timed("vbyte_ends", s, [&] { return launch_vb_decode(a, true, s); }))) != SVB_OK) return st;
+    if ((st = hip_status(timed("scan_offsets", s, [&] {
+             return launch_scan(a.tcount, sc + o_off, tiles, true, 0u, s, sc + o_tot, sc + o_scan);
+         }))) != SVB_OK)
+        return st;
+    return hip_status(timed("vbyte_decode", s, [&] { return launch_vb_decode(a, false, s); }));
+}
+
+// varint-GB decoding: chunk and tile maps, supertile maps, the chain across
+// supertiles and tiles, the decode pass.
+int do_gb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n > SVB_MAX_N) return SVB_ERR_INVALID;
+    if (err && !aligned4(err)) return SVB_ERR_INVALID;
+    if (n == 0) return SVB_OK;
+    if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
+    if (in_bytes < n + (n + 3) / 4) return SVB_ERR_INVALID;
+    const uint64_t tiles = gb_tiles(in_bytes), supers = gb_supers(tiles);
+    auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
+    const uint64_t o_cmap = 0;
+    const uint64_t o_tmap = o_cmap + up16(2 * 17 * 64 * tiles);
+    const uint64_t o_smap = o_tmap + up16(4 * 17 * tiles);
+    const uint64_t o_sentry = o_smap + up16(4 * 17 * supers);
+    const uint64_t o_sbase = o_sentry + up16(4 * supers);
+    const uint64_t o_tentry = o_sbase + up16(8 * supers);
+    const uint64_t o_tbase = o_tentry + up16(4 * tiles);
+    const uint64_t o_total = o_tbase + up16(8 * tiles);
+    const uint64_t need = o_total + 16;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *w;
+    int st = acquire_locked(s, &w);
+    if (st != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    uint8_t *sc = w->scratch;
+    GbDecodeArgs a;
+    a.in = in;
+    a.in_bytes = in_bytes;
+    a.n = n;
+    a.tiles = tiles;
+    a.supers = supers;
+    a.cmap = (uint16_t *)(sc + o_cmap);
+    a.tmap = (uint32_t *)(sc + o_tmap);
+    a.smap = (uint32_t *)(sc + o_smap);
+    a.sentry = (uint32_t *)(sc + o_sentry);
+    a.sbase = (uint64_t *)(sc + o_sbase);
+    a.tentry = (uint32_t *)(sc + o_tentry);
+    a.tbase = (uint64_t *)(sc + o_tbase);
+    a.total = (uint64_t *)(sc + o_total);
+    a.out = out;
+    a.err = err;
+    static const char *const names[] = {"varintgb_maps", "varintgb_super", "varintgb_top", "varintgb_tiles",
+                                        "varintgb_decode"};
+    for (int ph = kGbMap; ph <= kGbDecode; ++ph)
+        if ((st = hip_status(timed(names[ph], s, [&] { return launch_gb_decode(a, ph, s); }))) != SVB_OK) return st;
+    return SVB_OK;
+}
+
 }  // namespace svb
 
 using namespace svb;
@@ -613,6 +734,27 @@ int svb_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, con
 int svb_delta_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, const uint32_t *vals, uint32_t prev,
                      uint8_t *out, uint64_t *out_bytes, void *stream) {
     return do_append(n, in, in_bytes, k, vals, prev, true, out, out_bytes, stream);
+}
+
+uint64_t svb_vbyte_max_bytes(uint64_t n) { return 5 * n; }
+
+int svb_vbyte_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, void *stream) {
+    return do_cmp_encode(n, in, out, out_bytes, kFmtVByte, stream);
+}
+
+int svb_vbyte_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err, void *stream) {
+    return do_vb_decode(n, in, in_bytes, out, err, stream);
+}
+
+uint64_t svb_varintgb_max_bytes(uint64_t n) { return (n + 3) / 4 + 4 * n; }
+
+int svb_varintgb_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint64_t *out_bytes, void *stream) {
+    return do_cmp_encode(n, in, out, out_bytes, kFmtVarintGB, stream);
+}
+
+int svb_varintgb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t *err,
+                        void *stream) {
+    return do_gb_decode(n, in, in_bytes, out, err, stream);
 }
 
 int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,

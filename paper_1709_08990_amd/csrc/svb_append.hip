@@ -17,21 +17,6 @@ namespace svb {
 
 namespace {
 
-// 16 bytes starting at byte o (0..15) of the 32 bytes lo:hi (little-endian).
-__device__ __forceinline__ u32x4a shift_window(const u32x4a &lo, const u32x4a &hi, uint32_t o) {
-    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-    const uint32_t q = o >> 2, rb = o & 3u;
-    uint32_t r[4];
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) {
-        // dwords q + i and q + i + 1, q in 0..3
-        const uint32_t a0 = q == 0 ? w[i] : q == 1 ? w[i + 1] : q == 2 ? w[i + 2] : w[i + 3];
-        const uint32_t a1 = q == 0 ? w[i + 1] : q == 1 ? w[i + 2] : q == 2 ? w[i + 3] : w[i + 4];
-        r[i] = __builtin_amdgcn_alignbyte(a1, a0, rb);
-    }
-    return u32x4a{r[0], r[1], r[2], r[3]};
-}
-
 struct CopyArgs {
     const uint8_t *src;
     uint8_t *dst;

@@ -171,4 +171,50 @@ hipError_t launch_merge_ctrl(const uint8_t *old_ctrl, const uint8_t *new_ctrl, u
                              hipStream_t s);
 hipError_t launch_fill(uint32_t *out, uint64_t n, uint32_t value, hipStream_t s);
 
+// The comparison formats of Table 1: VByte and varint-GB.
+constexpr int kFmtVByte = 0, kFmtVarintGB = 1;
+// Encoding: bytes per 1024-integer segment (sizes pass), a scan, the pack.
+struct CmpEncodeArgs {
+    const uint32_t *in;
+    uint64_t n;
+    uint8_t *out;
+    uint32_t *seg_bytes;
+    const uint64_t *seg_off;
+    uint64_t segs;
+    uint64_t *out_bytes;
+};
+hipError_t launch_cmp_encode(const CmpEncodeArgs &a, int fmt, bool sizes, hipStream_t s);
+// VByte decoding: integer ends per 1024-byte tile (count pass), a scan
+// (toff, total), the decode pass.
+struct VbDecodeArgs {
+    const uint8_t *in;
+    uint64_t in_bytes, n, tiles;
+    uint32_t *tcount;
+    const uint64_t *toff;
+    const uint64_t *total;
+    uint32_t *out;
+    uint32_t *err;
+};
+uint64_t vb_tiles(uint64_t in_bytes);
+hipError_t launch_vb_decode(const VbDecodeArgs &a, bool count, hipStream_t s);
+// varint-GB decoding, in five passes (kGbMap .. kGbDecode).
+enum GbPhase { kGbMap = 0, kGbSuper, kGbTop, kGbTiles, kGbDecode };
+struct GbDecodeArgs {
+    const uint8_t *in;
+    uint64_t in_bytes, n, tiles, supers;
+    uint16_t *cmap;    // 17 entries per 128-byte chunk
+    uint32_t *tmap;    // 17 entries per 8 KiB tile
+    uint32_t *smap;    // 17 entries per 64 tiles
+    uint32_t *sentry;  // chain entry and first block of each supertile
+    uint64_t *sbase;
+    uint32_t *tentry;  // ... and of each tile
+    uint64_t *tbase;
+    uint64_t *total;   // blocks starting inside the stream
+    uint32_t *out;
+    uint32_t *err;
+};
+uint64_t gb_tiles(uint64_t in_bytes);
+uint64_t gb_supers(uint64_t tiles);
+hipError_t launch_gb_decode(const GbDecodeArgs &a, int phase, hipStream_t s);
+
 }  // namespace svb
