@@ -557,6 +557,52 @@ def measure_append(svb, torch, np, inputs, steps, warmup, n=1 << 26, k=1 << 22):
                            "sample": "one append of the same streams, host memory"}}
 
 
+def measure_compare(svb, torch, np, inputs, steps, warmup, n=1 << 26, sweep_n=1 << 22):
+    """Stream VByte against the comparison formats of Table 1 on the same integers: the 2^26
+    document-id gaps of the headline workload, each format encoded and decoded on the device
+    (plain, no differential step), checked against the input; then the storage comparison (bits
+    per integer, and the extra over VByte) on 2^22 integers uniform below 2^b for a sweep of b."""
+    x = inputs.docid_gaps(n, seed=2)
+    x_dev = torch.from_numpy(x.view(np.int32)).cuda()
+    fmts = {"stream_vbyte": (svb.svb_max_compressed_bytes, svb.svb_encode, svb.svb_decode),
+            "vbyte": (svb.svb_vbyte_max_bytes, svb.svb_vbyte_encode, svb.svb_vbyte_decode),
+            "varint_gb": (svb.svb_varintgb_max_bytes, svb.svb_varintgb_encode, svb.svb_varintgb_decode)}
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    res = {"n": n, "workload": "document-id gaps of the delta decode workload (plain decode)"}
+    for name, (maxb, enc, dec) in fmts.items():
+        comp = torch.empty(maxb(n), dtype=torch.uint8, device="cuda")
+        ewall, ekms = timed_steps(svb, torch, lambda: enc(n, x_dev, comp, size), steps, warmup)
+        torch.cuda.synchronize()
+        nb = int(size.item())
+        out.zero_()
+        dwall, dkms = timed_steps(svb, torch, lambda: dec(n, comp, nb, out, err), steps, warmup)
+        ok = bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+        dms, ems = 1e3 * dwall / steps, 1e3 * ewall / steps
+        res[name] = {"bytes": nb, "bits_per_int": 8.0 * nb / n, "decode_ms": dms, "decode_uint32_per_s": n / (dms * 1e-3),
+                     "decode_GBps": gbs(nb + 4 * n, dms), "decode_kernels_ms": dkms, "encode_ms": ems,
+                     "encode_uint32_per_s": n / (ems * 1e-3), "encode_kernels_ms": ekms, "round_trip_ok": ok}
+        del comp
+    for name in ("vbyte", "varint_gb"):
+        res[name]["stream_vbyte_decode_speedup"] = res[name]["decode_ms"] / res["stream_vbyte"]["decode_ms"]
+    sweep = []
+    comp = torch.empty(svb.svb_vbyte_max_bytes(sweep_n), dtype=torch.uint8, device="cuda")
+    for b in (4, 7, 8, 12, 14, 16, 20, 21, 24, 28, 32):
+        xs = torch.from_numpy(inputs.bounded_gaps(sweep_n, b, seed=100 + b).view(np.int32)).cuda()
+        row = {"bits": b}
+        for name, (_, enc, _) in fmts.items():
+            enc(sweep_n, xs, comp, size)
+            torch.cuda.synchronize()
+            row[name] = 8.0 * int(size.item()) / sweep_n
+        row["stream_vbyte_extra"] = row["stream_vbyte"] - row["vbyte"]
+        row["varint_gb_extra"] = row["varint_gb"] - row["vbyte"]
+        sweep.append(row)
+    res["storage_bits_per_int"] = {"n": sweep_n, "values": "uniform in [0, 2^bits)", "rows": sweep}
+    del x_dev, out, comp
+    return res
+
+
 def build_pool(svb, torch, np, inputs, m, total, cap, seed):
     """Serving pool: m delta-coded posting lists (rank-size Zipf lengths in [1, cap] summing to
     `total`, sorted sets over [0, 2^31) drawn on the GPU), encoded by the batched encoder and
@@ -736,6 +782,7 @@ def main():
     ap.add_argument("--no-seek", action="store_true", help="skip the seek/select measurement")
     ap.add_argument("--no-append", action="store_true", help="skip the append measurement")
     ap.add_argument("--no-zero-control", action="store_true", help="skip the zero-control variant measurement")
+    ap.add_argument("--no-compare", action="store_true", help="skip the VByte / varint-GB comparison")
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -743,11 +790,11 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
                     "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control --no-compare")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
                     "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
-                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control")
+                    "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control --no-compare")
     ap.add_argument("--trace-bench-json", default=None,
                     help="bench line printed by the traced command (for --summarize-trace)")
     args = ap.parse_args()
@@ -867,6 +914,14 @@ def main():
         line["zero_control"] = rz
         log("zero-control variant: general %.4f ms, zero-control %.4f ms (%.2fx)"
             % (rz["variant0"]["ms_per_call"], rz["variant1"]["ms_per_call"], rz["speedup"]))
+    if not args.no_compare:
+        log("comparison formats: Stream VByte, VByte, varint-GB on the 2^26 document-id gaps")
+        rc = measure_compare(svb, torch, np, inputs, max(5, args.steps // 2), 2)
+        assert all(rc[f]["round_trip_ok"] for f in ("stream_vbyte", "vbyte", "varint_gb")), "comparison mismatch"
+        line["compare"] = rc
+        log("decode ms: Stream VByte %.4f, VByte %.4f, varint-GB %.4f; bits/int %.2f / %.2f / %.2f"
+            % (rc["stream_vbyte"]["decode_ms"], rc["vbyte"]["decode_ms"], rc["varint_gb"]["decode_ms"],
+               rc["stream_vbyte"]["bits_per_int"], rc["vbyte"]["bits_per_int"], rc["varint_gb"]["bits_per_int"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
         rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)

@@ -261,3 +261,11 @@ def random_bytes(n, seed=7):
 def random_u32(n, seed=8):
     rng = np.random.default_rng(seed)
     return rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+
+
+def bounded_gaps(n, bits, seed=13):
+    """Integers drawn uniformly from [0, 2^bits): a list whose deltas all fit in `bits` bits, the
+    compressibility axis along which Section 5 compares the byte-oriented formats (VByte's bits per
+    integer on the horizontal axis of its size and speed figures)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << bits, size=n, dtype=np.uint64).astype(np.uint32)
