@@ -38,6 +38,12 @@ constexpr uint32_t kGbTile = kGbChunk * kWave;     // 8192 bytes per wave
 constexpr uint32_t kGbEntries = 17;                // a block spans at most 17 bytes
 constexpr uint32_t kGbEnd = 31;                    // exit marker: the walk reached in_bytes
 constexpr uint32_t kGbStage = kGbTile + 32;        // a tile and the bytes its last blocks may spill into
+// In LDS a chunk takes 132 bytes (33 dwords, an odd count), so that the 64
+// lanes, each reading its own chunk at the same offset, hit different banks
+// (a 128-byte pitch puts them all in one).
+constexpr uint32_t kGbPitch = kGbChunk + 4;
+constexpr uint32_t kGbLdsMap = kWave * kGbPitch;          // a tile
+constexpr uint32_t kGbLdsDecode = (kWave + 1) * kGbPitch; // a tile and its spill bytes
 constexpr uint32_t kStageMax = 5 * kSegInts;       // bytes of one encoded segment, at most
 
 __device__ __forceinline__ uint64_t wave_index() { return (uint64_t)blockIdx.x * kWaves + threadIdx.x / kWave; }
@@ -253,13 +259,23 @@ __global__ __launch_bounds__(kThreads) void vb_decode_kernel(VbDecodeArgs a) {
 
 // ---------------------------------------------------------------- varint-GB decoder
 
+// LDS offset of byte x of a tile (chunks kGbPitch apart).
+__device__ __forceinline__ uint32_t gb_lds(uint32_t x) { return (x / kGbChunk) * kGbPitch + x % kGbChunk; }
+
 // Stages bytes [base, base + len) of the stream (len a multiple of 16) at
-// stage[0..len); bytes outside the stream are unspecified.
+// stage[gb_lds(0 .. len)); bytes outside the stream are unspecified.
 __device__ __forceinline__ void gb_stage(const GbDecodeArgs &a, uint64_t base, uint32_t len, uint8_t *stage,
                                          uint32_t lane) {
     for (uint32_t i = lane; 16 * i < len; i += kWave) {
         const uint64_t pos = base + 16ull * i;
-        if (pos < a.in_bytes) *(u32x4a *)(stage + 16 * i) = load_window(a.in, a.in_bytes, pos);
+        if (pos < a.in_bytes) {
+            const u32x4a w = load_window(a.in, a.in_bytes, pos);
+            uint32_t *d = (uint32_t *)(stage + gb_lds(16 * i));
+            d[0] = w.x;
+            d[1] = w.y;
+            d[2] = w.z;
+            d[3] = w.w;
+        }
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -270,7 +286,7 @@ __device__ __forceinline__ uint32_t gb_block_bytes(uint32_t c) { return 1u + con
 // Chunk maps (entry e -> exit | blocks << 5) and the tile map (entry ->
 // exit | blocks << 8) of one 8 KiB tile.
 __global__ __launch_bounds__(kThreads) void gb_map_kernel(GbDecodeArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves][kGbTile];
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves][kGbLdsMap];
     __shared__ uint16_t s_map[kWaves][kWave * kGbEntries];
     const uint64_t tile = wave_index();
     if (tile >= a.tiles) return;
@@ -280,6 +296,7 @@ __global__ __launch_bounds__(kThreads) void gb_map_kernel(GbDecodeArgs a) {
     const uint64_t base = tile * kGbTile;
     gb_stage(a, base, kGbTile, stage, lane);
     const uint64_t cbase = base + (uint64_t)lane * kGbChunk;
+    const uint8_t *chunk = stage + lane * kGbPitch;
     for (uint32_t e = 0; e < kGbEntries; ++e) {
         uint32_t p = e, cnt = 0, exit = kGbEnd;
         for (;;) {
@@ -288,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void gb_map_kernel(GbDecodeArgs a) {
                 break;
             }
             if (cbase + p >= a.in_bytes) break;
-            p += gb_block_bytes(stage[lane * kGbChunk + p]);
+            p += gb_block_bytes(chunk[p]);
             ++cnt;
         }
         const uint16_t v = (uint16_t)(exit | (cnt << 5));
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void gb_tiles_kernel(GbDecodeArgs a) {
 // Decodes the blocks that start in one tile: the chain across its chunks from
 // the tile's entry, then each lane decodes the blocks of its chunk.
 __global__ __launch_bounds__(kThreads) void gb_decode_kernel(GbDecodeArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves][kGbStage];
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves][kGbLdsDecode];
     __shared__ uint16_t s_map[kWaves][kWave * kGbEntries];
     __shared__ uint32_t s_entry[kWaves][kWave], s_first[kWaves][kWave];
     const uint64_t tile = wave_index();
@@ -417,8 +434,7 @@ __global__ __launch_bounds__(kThreads) void gb_decode_kernel(GbDecodeArgs a) {
     bool bad = false;
     if (p != kGbEnd) {
         while (p < kGbChunk && cbase + p < a.in_bytes && b < nblocks) {
-            const uint32_t at = lane * kGbChunk + p;
-            const uint32_t c = stage[at];
+            const uint32_t c = stage[lane * kGbPitch + p];
             const uint64_t left = a.n - 4 * b;
             const uint32_t r = left < 4 ? (uint32_t)left : 4u;
             const uint32_t size = 1u + control_data_bytes(c, r);
@@ -427,13 +443,13 @@ __global__ __launch_bounds__(kThreads) void gb_decode_kernel(GbDecodeArgs a) {
                 break;
             }
             uint32_t v[4] = {0u, 0u, 0u, 0u};
-            uint32_t q = at + 1;
+            uint32_t q = lane * kGbChunk + p + 1;  // tile offset of the block's data
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 if (j < r) {
                     const uint32_t len = ((c >> (2 * j)) & 3u) + 1u;
                     uint32_t val = 0;
-                    for (uint32_t t = 0; t < len; ++t) val |= (uint32_t)stage[q + t] << (8 * t);
+                    for (uint32_t t = 0; t < len; ++t) val |= (uint32_t)stage[gb_lds(q + t)] << (8 * t);
                     v[j] = val;
                     q += len;
                 }
