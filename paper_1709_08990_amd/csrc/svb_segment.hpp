@@ -77,14 +77,23 @@ __device__ __forceinline__ SegPlan plan_segment(const DecodeArgs &p, uint64_t s,
     SegPlan sp;
     sp.sc = sc;
     const bool full = segment_full(p, s);
-    uint32_t run = 0;
+    uint32_t nb[4];
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t m = full ? 4u : block_ints(p, s, k, lane);
-        const uint32_t nb = m + __builtin_popcount(sc.c[k]) + __builtin_popcount(sc.c[k] & 0xAAu);
-        const uint32_t incl = wave_incl_scan(nb);
-        sp.off[k] = run + incl - nb;
-        run += wave_last(incl);
+        nb[k] = m + __builtin_popcount(sc.c[k]) + __builtin_popcount(sc.c[k] & 0xAAu);
+    }
+    // Two rows per wave scan, one in each 16-bit half: a row's bytes total
+    // at most 64 x 16 = 1024, so the low half never carries into the high.
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k += 2) {
+        const uint32_t incl = wave_incl_scan(nb[k] | (nb[k + 1] << 16));
+        const uint32_t tot = wave_last(incl);
+        sp.off[k] = run + (incl & 0xFFFFu) - nb[k];
+        run += tot & 0xFFFFu;
+        sp.off[k + 1] = run + (incl >> 16) - nb[k + 1];
+        run += tot >> 16;
     }
     sp.total = run;
     return sp;
