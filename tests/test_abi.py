@@ -67,3 +67,34 @@ def test_argument_errors_are_synchronous():
     assert L.svb_encode(0, None, None, None, None) == 0               # n = 0, nothing to write
     assert L.svb_decode(0, None, 0, None, None, None) == 0
     assert L.svb_copy_u32(4, 4098, 4096, None) == -1
+
+
+def test_comparison_format_sizes_and_argument_errors():
+    """VByte and varint-GB entry points: worst-case sizes, and the checks that return before any
+    HIP call."""
+    assert svb.svb_vbyte_max_bytes(7) == 35
+    assert svb.svb_varintgb_max_bytes(5) == 2 + 20
+    L = svb.lib()
+    for dec in (L.svb_vbyte_decode, L.svb_varintgb_decode):
+        assert dec(5, None, 10, None, None, None) == -1           # null pointers
+        assert dec(8, 4096, 64, 4098, None, None) == -1           # misaligned uint32 out
+        assert dec(1 << 41, 4096, 1 << 50, 4096, None, None) == -1  # n too large
+        assert dec(0, None, 0, None, None, None) == 0
+    assert L.svb_vbyte_decode(9, 4096, 8, 4096, None, None) == -1      # fewer bytes than integers
+    assert L.svb_varintgb_decode(8, 4096, 9, 4096, None, None) == -1   # below n + ceil(n/4)
+    for enc in (L.svb_vbyte_encode, L.svb_varintgb_encode):
+        assert enc(4, 4098, 4096, None, None) == -1               # misaligned uint32 in
+        assert enc(4, 4096, 4096, 4100, None) == -1               # misaligned out_bytes
+        assert enc(0, None, None, None, None) == 0
+
+
+def test_decoder_variant_is_checked():
+    assert svb.lib().svb_set_decode_variant(1, 2) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
