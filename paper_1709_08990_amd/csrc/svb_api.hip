@@ -172,9 +172,14 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     ga.gbytes = (uint32_t *)(sc + o_gbytes);
     ga.seg_loc = nullptr;
     if ((st = hip_status(timed("group_bytes", s, [&] { return launch_group_bytes(ga, s); }))) != SVB_OK) return st;
-    if ((st = hip_status(timed("scan_offsets", s, [&] { return launch_scan(ga.gbytes, sc + o_goff, groups, true, 0u, s, nullptr, sc + o_scan); }))) !=
-        SVB_OK)
+    // offsets below 2^32 (a data stream under 4 GiB) scan in 32 bits: half
+    // the bytes written and read
+    const bool off32 = in_bytes < (1ull << 32);
+    if ((st = hip_status(timed("scan_offsets", s, [&] {
+             return launch_scan(ga.gbytes, sc + o_goff, groups, !off32, 0u, s, nullptr, sc + o_scan);
+         }))) != SVB_OK)
         return st;
+    const uint32_t *goff32 = off32 ? (const uint32_t *)(sc + o_goff) : nullptr;
 
     DecodeArgs a = {};
     a.in = in;
@@ -188,7 +193,8 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     a.gvpre = (const uint32_t *)(sc + o_gvpre);
     if (delta) {
         // value sum of every group, then start + their exclusive prefix
-        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s, zc); }))) != SVB_OK)
+        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s, zc, goff32); }))) !=
+            SVB_OK)
             return st;
         if ((st = hip_status(timed("scan_sums", s, [&] {
                  return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s, nullptr, sc + o_scan);
@@ -196,7 +202,8 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
             return st;
     }
     return hip_status(
-        timed(delta ? "decode_delta" : "decode", s, [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc); }));
+        timed(delta ? "decode_delta" : "decode", s,
+              [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc, goff32); }));
 }
 
 // Times the two decoder variants on the caller's stream (median of five

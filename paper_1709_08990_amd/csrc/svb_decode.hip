@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 //   ZC: rows of all-zero control bytes take the widening path of
 //       extract_segment (the zero-control variant).
 template <int MODE, bool ZC>
-__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
+__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const uint32_t *goff32) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
     const uint64_t s_end = s0 + kGroupSegs < segs ? s0 + kGroupSegs : segs;
     uint32_t carry = (MODE == kDelta) ? p.gvpre[g] : 0u;
     Walker<MODE == kPlain ? 2 : 1> w;  // plain decoding waits on memory: two segments in flight
-    walker_begin(p, w, s0, s_end, p.goff[g], lane);
+    walker_begin(p, w, s0, s_end, goff32 ? (uint64_t)goff32[g] : p.goff[g], lane);
     for (uint64_t s = s0; s < s_end; ++s) {
         SegPlan seg;
         uint32_t sh16;
@@ -106,23 +106,23 @@ hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc) {
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc, const uint32_t *goff32) {
     const uint32_t grid = (uint32_t)((a.groups + kWaves - 1) / kWaves);
     if (mode == kPlain) {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kPlain, true>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kPlain, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
         else
-            hipLaunchKernelGGL((decode_kernel<kPlain, false>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kPlain, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
     } else if (mode == kDelta) {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kDelta, true>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kDelta, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
         else
-            hipLaunchKernelGGL((decode_kernel<kDelta, false>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kDelta, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
     } else {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kSums, true>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kSums, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
         else
-            hipLaunchKernelGGL((decode_kernel<kSums, false>), dim3(grid), dim3(kThreads), 0, s, a);
+            hipLaunchKernelGGL((decode_kernel<kSums, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
     }
     return hipGetLastError();
 }

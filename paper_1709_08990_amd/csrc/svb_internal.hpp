@@ -54,7 +54,10 @@ uint64_t scan_scratch_bytes(uint64_t m);
 hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
                        void *total = nullptr, void *scratch = nullptr);
 // zc: the zero-control variant (rows of all-zero control bytes widen bytes).
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false);
+// goff32 (may be null): 32-bit group offsets, used instead of a.goff (a data
+// stream below 4 GiB).
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false,
+                         const uint32_t *goff32 = nullptr);
 
 // Batched calls.  A task is one 1024-integer segment of one list; each wave of
 // the main pass takes `chunk` consecutive tasks.

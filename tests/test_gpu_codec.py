@@ -166,6 +166,30 @@ def test_random_stream_decode(n):
     np.testing.assert_array_equal(dvals, dref)
 
 
+def test_buffer_of_4gib_takes_64bit_offsets():
+    """A buffer declared 4 GiB or larger switches the group offsets to 64 bits (below that they
+    are 32-bit); the stream at its start decodes the same, plain and delta, and the bytes after
+    it are not read into any value."""
+    x = inputs.docids(250_001, seed=14)[0]
+    big = torch.empty((1 << 32) + 64, dtype=torch.uint8, device="cuda")
+    for delta in (False, True):
+        s = oracle.encode(x, delta=delta)
+        want, _ = oracle.decode(s, x.size, delta=delta)
+        big[:s.size].copy_(to_dev_u8(s))
+        big[s.size:s.size + 4096].fill_(0xFF)
+        log_case("4 GiB buffer", "delta=%s" % delta)
+        out = torch.zeros(x.size, dtype=torch.int32, device="cuda")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        if delta:
+            svb.svb_delta_decode(x.size, big, big.numel(), out, 0, err)
+        else:
+            svb.svb_decode(x.size, big, big.numel(), out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        np.testing.assert_array_equal(u32_host(out), want)
+    del big
+
+
 @pytest.mark.parametrize("shift", [1, 2, 3, 5, 13])
 def test_misaligned_streams(shift):
     """Streams at any byte alignment, and trailing bytes after the stream."""
