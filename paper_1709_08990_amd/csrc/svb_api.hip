@@ -118,12 +118,16 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
     if ((st = hip_status(timed("encode_sizes", s, [&] { return launch_encode_sizes(e, delta, seg_bytes, segs, s); }))) !=
         SVB_OK)
         return st;
+    // offsets that fit 32 bits whatever the values (n below about 1.01e9) scan
+    // in 32 bits: half the bytes written and read
+    const bool off32 = (n + 3) / 4 + 4 * n < (1ull << 32);
     if ((st = hip_status(timed("scan_offsets", s, [&] {
-             return launch_scan(seg_bytes, seg_off, segs, true, 0u, s, nullptr, sc + o_scan);
+             return launch_scan(seg_bytes, seg_off, segs, !off32, 0u, s, nullptr, sc + o_scan);
          }))) != SVB_OK)
         return st;
+    const uint32_t *seg_off32 = off32 ? (const uint32_t *)seg_off : nullptr;
     return hip_status(timed(delta ? "encode_delta" : "encode", s,
-                            [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s); }));
+                            [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s, seg_off32); }));
 }
 
 // Decoder variant per (device, delta): true = the zero-control variant.

@@ -40,15 +40,17 @@ __global__ __launch_bounds__(kThreads) void encode_sizes_kernel(EncodeStream e, 
 }
 
 template <bool DELTA>
-__global__ __launch_bounds__(kThreads) void encode_pack_kernel(EncodeStream e, const uint64_t *seg_off, uint64_t segs,
+__global__ __launch_bounds__(kThreads) void encode_pack_kernel(EncodeStream e, const uint64_t *seg_off,
+                                                               const uint32_t *seg_off32, uint64_t segs,
                                                                uint64_t *out_bytes) {
     __shared__ __attribute__((aligned(16))) uint32_t s_stage[kWaves * (kEncStageBytes / 4)];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint64_t s = (uint64_t)blockIdx.x * kWaves + wave;
     if (s >= segs) return;
-    const uint32_t t = encode_segment<DELTA>(e, s, seg_off[s], lane, s_stage + wave * (kEncStageBytes / 4));
-    if (s == segs - 1 && lane == 0 && out_bytes) *out_bytes = (e.n + 3) / 4 + seg_off[s] + t;
+    const uint64_t off = seg_off32 ? (uint64_t)seg_off32[s] : seg_off[s];
+    const uint32_t t = encode_segment<DELTA>(e, s, off, lane, s_stage + wave * (kEncStageBytes / 4));
+    if (s == segs - 1 && lane == 0 && out_bytes) *out_bytes = (e.n + 3) / 4 + off + t;
 }
 
 __global__ __launch_bounds__(kThreads) void copy_kernel(const uint32_t *in, uint32_t *out, uint64_t n) {
@@ -80,12 +82,14 @@ hipError_t launch_encode_sizes(const EncodeStream &e, bool delta, uint32_t *seg_
 }
 
 hipError_t launch_encode_pack(const EncodeStream &e, bool delta, const uint64_t *seg_off, uint64_t segs,
-                              uint64_t *out_bytes, hipStream_t s) {
+                              uint64_t *out_bytes, hipStream_t s, const uint32_t *seg_off32) {
     const uint32_t grid = (uint32_t)((segs + kWaves - 1) / kWaves);
     if (delta)
-        hipLaunchKernelGGL((encode_pack_kernel<true>), dim3(grid), dim3(kThreads), 0, s, e, seg_off, segs, out_bytes);
+        hipLaunchKernelGGL((encode_pack_kernel<true>), dim3(grid), dim3(kThreads), 0, s, e, seg_off, seg_off32, segs,
+                           out_bytes);
     else
-        hipLaunchKernelGGL((encode_pack_kernel<false>), dim3(grid), dim3(kThreads), 0, s, e, seg_off, segs, out_bytes);
+        hipLaunchKernelGGL((encode_pack_kernel<false>), dim3(grid), dim3(kThreads), 0, s, e, seg_off, seg_off32, segs,
+                           out_bytes);
     return hipGetLastError();
 }
 

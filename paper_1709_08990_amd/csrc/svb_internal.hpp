@@ -162,8 +162,9 @@ struct EncodeStream {
     uint32_t start;
 };
 hipError_t launch_encode_sizes(const EncodeStream &e, bool delta, uint32_t *seg_bytes, uint64_t segs, hipStream_t s);
+// seg_off32 (may be null): 32-bit segment offsets, used instead of seg_off.
 hipError_t launch_encode_pack(const EncodeStream &e, bool delta, const uint64_t *seg_off, uint64_t segs,
-                              uint64_t *out_bytes, hipStream_t s);
+                              uint64_t *out_bytes, hipStream_t s, const uint32_t *seg_off32 = nullptr);
 hipError_t launch_copy(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t s);
 // Append: a byte copy at any alignments (the count is len, or *len_dev -
 // len_sub when len_dev is set, at most len; size_out, if set, receives

@@ -166,6 +166,34 @@ def test_random_stream_decode(n):
     np.testing.assert_array_equal(dvals, dref)
 
 
+@pytest.mark.slow
+def test_encode_with_64bit_segment_offsets():
+    """1.05e9 integers: the encoder's worst case (4.25 bytes per integer) passes 4 GiB, so its
+    segment offsets are 64-bit
+    (below that they are 32-bit).  Checked by what holds at any size: integer i is i mod 256, one
+    byte each, so every control byte is 0, data byte i is i mod 256 and the size is ceil(n/4) + n;
+    the stream then decodes back to the input."""
+    n = 1_050_000_000
+    log_case("encode with 64-bit segment offsets", "n=%d" % n)
+    x = torch.arange(n, dtype=torch.int32, device="cuda").bitwise_and_(0xFF)
+    cap = svb.svb_max_compressed_bytes(n)
+    assert cap >= 1 << 32
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_encode(n, x, out, size)
+    torch.cuda.synchronize()
+    nc = (n + 3) // 4
+    assert int(size.item()) == nc + n
+    assert int(torch.count_nonzero(out[:nc]).item()) == 0
+    assert bool(torch.equal(out[nc:nc + n], x.to(torch.uint8)))
+    back = torch.empty(n, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    svb.svb_decode(n, out, nc + n, back, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and bool(torch.equal(back, x))
+    del x, out, back
+
+
 def test_buffer_of_4gib_takes_64bit_offsets():
     """A buffer declared 4 GiB or larger switches the group offsets to 64 bits (below that they
     are 32-bit); the stream at its start decodes the same, plain and delta, and the bytes after
