@@ -154,3 +154,16 @@ def test_empty_input():
         getattr(svb, dec)(0, None, 0, None)
         torch.cuda.synchronize()
         assert int(size.item()) == 0
+
+
+def test_varintgb_chain_across_many_supertiles():
+    """2^25 document-id gaps (about 42 MB of varint-GB, 82 supertiles of 512 KiB): the true chain
+    is followed across more supertiles than one pass of the top-level wave holds (64)."""
+    n = 1 << 25
+    x = inputs.docid_gaps(n, seed=15)
+    s = oracle.varintgb_encode(x)
+    assert s.size > 64 * 512 * 1024
+    log_case("varint-GB many supertiles", "n=%d" % n, "bytes=%d" % s.size)
+    got, err = decode_gpu("varintgb", s, n, shift=5)
+    assert err == 0
+    np.testing.assert_array_equal(got, x)
