@@ -156,14 +156,16 @@ def test_empty_input():
         assert int(size.item()) == 0
 
 
-def test_varintgb_chain_across_many_supertiles():
-    """2^25 document-id gaps (about 42 MB of varint-GB, 82 supertiles of 512 KiB): the true chain
-    is followed across more supertiles than one pass of the top-level wave holds (64)."""
+@pytest.mark.parametrize("fmt", sorted(FORMATS))
+def test_streams_of_tens_of_megabytes(fmt):
+    """2^25 document-id gaps: for varint-GB about 42 MB, 82 supertiles of 512 KiB, so the true
+    chain is followed across more supertiles than one pass of the top-level wave holds (64); for
+    VByte about 34 MB, whose 1 KiB tiles take the multi-workgroup scan."""
     n = 1 << 25
     x = inputs.docid_gaps(n, seed=15)
-    s = oracle.varintgb_encode(x)
-    assert s.size > 64 * 512 * 1024
-    log_case("varint-GB many supertiles", "n=%d" % n, "bytes=%d" % s.size)
-    got, err = decode_gpu("varintgb", s, n, shift=5)
+    s = FORMATS[fmt][0](x)
+    assert s.size > 32 * 1024 * 1024
+    log_case("compare tens of MB", fmt, "n=%d" % n, "bytes=%d" % s.size)
+    got, err = decode_gpu(fmt, s, n, shift=5)
     assert err == 0
     np.testing.assert_array_equal(got, x)
