@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
 // segment to segment, and the next segment's data is in flight while one is
 // summed.  Writes each task's sum of stored differences to ivsum (0 for the
 // last task of a list, whose sum no carry needs).
-constexpr uint32_t kSumsChunk = 8;  // measured: 8 tasks 209 us on C4, 16 213-228, 32 230
+constexpr uint32_t kSumsChunk = 8;  // measured on C4: 8 tasks 175-179 us, 4 186-188, 6 178-180, 16 and 32 slower
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_sums_runs_kernel(
     BatchArgs a) {
