@@ -235,10 +235,11 @@ def kernel_means(svb):
 
 def timed_steps(svb, torch, fn, steps, warmup):
     """`warmup` untimed calls, then the timed region: `steps` calls between two device
-    synchronisations (wall clock; whole-job throughput), then the same `steps` calls again with
-    the library recording HIP events around each kernel on the launch stream (per-kernel
-    durations; the event records add a few microseconds per kernel, which is why the wall-clock
-    region runs without them).  Returns (wall seconds, per-kernel mean ms)."""
+    synchronisations (wall clock), then the same `steps` calls again with the library recording
+    HIP events around each kernel on the launch stream (per-kernel durations; the event records
+    add a few microseconds per kernel, which is why the wall-clock region runs without them).
+    Back to back, no cache flush: inputs that fit the 256 MB MALL stay there.  Returns (wall
+    seconds, per-kernel mean ms)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -256,11 +257,61 @@ def timed_steps(svb, torch, fn, steps, warmup):
     return wall, kernel_means(svb)
 
 
+MIN_REPS = 21
+
+
+def protocol_steps(svb, torch, fn, steps, warmup, flush):
+    """The measurement protocol: `warmup` untimed calls, then the timed region of exactly `steps`
+    calls between two device synchronisations, each call preceded by `flush` (a 1 GiB write that
+    evicts the L2s and the 256 MB MALL) and bracketed by events on the current stream; more
+    flushed calls until at least 21 have been timed.  The call time is the median of the event
+    durations.  Then the same number of flushed calls with the library's per-kernel HIP events
+    (median per kernel name), and `steps` calls back to back without flushing (mean, for
+    reference).  Returns a dict."""
+    for _ in range(warmup):
+        flush()
+        fn()
+    reps = max(steps, MIN_REPS)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (a, b) in enumerate(ev):
+        flush()
+        a.record()
+        fn()
+        b.record()
+        if i + 1 == steps:
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    svb.svb_kernel_times()  # drop stale records
+    svb.svb_set_kernel_timing(True)
+    for _ in range(reps):
+        flush()
+        fn()
+    torch.cuda.synchronize()
+    svb.svb_set_kernel_timing(False)
+    per = collections.defaultdict(list)
+    for name, t in svb.svb_kernel_times(cap=1 << 16):
+        per[name].append(t)
+    kms = {k: sorted(v)[len(v) // 2] for k, v in per.items()}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    unflushed = 1e3 * (time.perf_counter() - t1) / steps
+    return {"median_ms": ms[len(ms) // 2], "reps": reps, "min_ms": ms[0], "max_ms": ms[-1],
+            "timed_region_s": wall, "kernels_ms": kms, "unflushed_mean_ms": unflushed}
+
+
 def gbs(nbytes, ms):
     return nbytes / (ms * 1e-3) / 1e9
 
 
-def measure_delta(svb, torch, x_dev, steps, warmup, flush_buf=None):
+def measure_delta(svb, torch, x_dev, steps, warmup, flush):
+    """Delta decode and delta encode of one array under the protocol (flushed median)."""
     n = x_dev.numel()
     comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
     size = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -274,32 +325,30 @@ def measure_delta(svb, torch, x_dev, steps, warmup, flush_buf=None):
     def dec():
         svb.svb_delta_decode(n, comp, nbytes, out, 0, err)
 
-    wall, kms = timed_steps(svb, torch, dec, steps, warmup)
+    pr = protocol_steps(svb, torch, dec, steps, warmup, flush)
     ok = bool(torch.equal(out, x_dev)) and int(err.item()) == 0
-    call_ms = 1e3 * wall / steps
+    call_ms = pr["median_ms"]
     res = {"n": n, "compressed_bytes": nbytes, "bits_per_int": 8.0 * nbytes / n, "alg_bytes_per_call": alg,
-           "wall_s": wall, "ms_per_call": call_ms, "round_trip_ok": ok,
+           "ms_per_call": call_ms, "round_trip_ok": ok, "protocol": pr,
            "uint32_per_s": n / (call_ms * 1e-3), "call_GBps": gbs(alg, call_ms),
-           "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS, "kernels_ms": kms}
-    if flush_buf is not None:
-        fl = lambda: svb.svb_fill_u32(flush_buf.numel(), flush_buf, 0)
-        _, fms = event_loop(dec, max(3, steps // 2), torch, before=fl)
-        res["flushed"] = {"ms_per_call": fms, "GBps": gbs(alg, fms), "frac_of_peak": gbs(alg, fms) / HBM_PEAK_GBS,
-                          "note": "1 GiB fill before each call evicts L2 and the 256 MB MALL"}
+           "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS, "kernels_ms": pr["kernels_ms"],
+           "unflushed": {"ms_per_call": pr["unflushed_mean_ms"],
+                         "frac_of_peak": gbs(alg, pr["unflushed_mean_ms"]) / HBM_PEAK_GBS,
+                         "note": "mean of back-to-back calls, no cache flush"}}
 
     def enc():
         svb.svb_delta_encode(n, x_dev, comp, 0, size)
 
-    ewall, ekms = timed_steps(svb, torch, enc, steps, max(1, warmup // 2))
-    ems = 1e3 * ewall / steps
+    ep = protocol_steps(svb, torch, enc, steps, max(1, warmup // 2), flush)
+    ems = ep["median_ms"]
     res["encode"] = {"ms_per_call": ems, "uint32_per_s": n / (ems * 1e-3), "GBps": gbs(alg, ems),
-                     "frac_of_peak": gbs(alg, ems) / HBM_PEAK_GBS, "kernels_ms": ekms,
-                     "size_ok": int(size.item()) == nbytes}
+                     "frac_of_peak": gbs(alg, ems) / HBM_PEAK_GBS, "kernels_ms": ep["kernels_ms"],
+                     "unflushed_ms": ep["unflushed_mean_ms"], "size_ok": int(size.item()) == nbytes}
     del comp, out
     return res
 
 
-def measure_plain(svb, torch, x_dev, steps, warmup):
+def measure_plain(svb, torch, x_dev, steps, warmup, flush):
     n = x_dev.numel()
     comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
     size = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -308,13 +357,13 @@ def measure_plain(svb, torch, x_dev, steps, warmup):
     nbytes = int(size.item())
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     alg = nbytes + 4 * n
-    wall, kms = timed_steps(svb, torch, lambda: svb.svb_decode(n, comp, nbytes, out), steps, warmup)
+    pr = protocol_steps(svb, torch, lambda: svb.svb_decode(n, comp, nbytes, out), steps, warmup, flush)
     ok = bool(torch.equal(out, x_dev))
-    call_ms = 1e3 * wall / steps
+    call_ms = pr["median_ms"]
     del comp, out
     return {"n": n, "compressed_bytes": nbytes, "ms_per_call": call_ms, "uint32_per_s": n / (call_ms * 1e-3),
             "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
-            "kernels_ms": kms, "round_trip_ok": ok}
+            "kernels_ms": pr["kernels_ms"], "unflushed_ms": pr["unflushed_mean_ms"], "round_trip_ok": ok}
 
 
 def measure_copy(svb, torch, steps):
@@ -770,8 +819,92 @@ def run_cpu_baseline(x, min_seconds=10.0):
             "host_cpu": model, "host_threads_available": ncpu}
 
 
+ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched")
+
+
+def profile_only(kind, steps, warmup):
+    """Runs one kind of call only (`warmup` + `steps` calls, each after the 1 GiB cache-evicting
+    fill), for rocprofv3 runs that should see nothing else: delta26 / delta28 (delta decode of the
+    document ids at 2^26 / 2^28), plain28 (plain decode of 2^28 integers of unpredictable length),
+    encode28 (delta encode of the 2^28 document ids), batched (delta decode of the 200,000 posting
+    lists).  Prints one JSON line with the median call time by torch events."""
+    import numpy as np
+    import torch
+
+    import paper_1709_08990_amd as svb
+    from paper_1709_08990_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    svb.lib()
+    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    fl = lambda: svb.svb_fill_u32(flush.numel(), flush, 0)
+    if kind == "batched":
+        vals, offs = inputs.posting_lists()
+        m = offs.size - 1
+        counts = np.diff(offs).astype(np.uint64)
+        total = int(counts.sum())
+        x_dev = torch.from_numpy(vals.view(np.int32)).cuda()
+        del vals
+        caps = (counts + 3) // 4 + 4 * counts
+        comp_off = np.zeros(m, dtype=np.uint64)
+        np.cumsum(caps[:-1], out=comp_off[1:])
+        u64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+        d_counts, d_in_off, d_comp_off = u64(counts), u64(offs[:-1]), u64(comp_off)
+        comp = torch.empty(int(caps.sum()), dtype=torch.uint8, device="cuda")
+        sizes = torch.empty(m, dtype=torch.int64, device="cuda")
+        starts = torch.zeros(m, dtype=torch.int32, device="cuda")
+        out = torch.empty(total, dtype=torch.int32, device="cuda")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        svb.svb_encode_batch(m, d_counts, d_in_off, x_dev, d_comp_off, comp, sizes, starts, total)
+        args = (m, d_counts, d_comp_off, sizes, comp, d_in_off, out, starts, total, err)
+        n = total
+        fn = lambda: svb.svb_decode_batch(*args)
+        check = lambda: bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+    else:
+        n = 1 << (26 if kind == "delta26" else 28)
+        x = inputs.stress_lengths(n, seed=3) if kind == "plain28" else inputs.docids(n, seed=2)[0]
+        x_dev = torch.from_numpy(x.view(np.int32)).cuda()
+        del x
+        comp = torch.empty(svb.svb_max_compressed_bytes(n), dtype=torch.uint8, device="cuda")
+        size = torch.zeros(1, dtype=torch.int64, device="cuda")
+        delta = kind != "plain28"
+        (svb.svb_delta_encode(n, x_dev, comp, 0, size) if delta else svb.svb_encode(n, x_dev, comp, size))
+        torch.cuda.synchronize()
+        nb = int(size.item())
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        if kind == "encode28":
+            fn = lambda: svb.svb_delta_encode(n, x_dev, comp, 0, size)
+            check = lambda: int(size.item()) == nb
+        elif delta:
+            fn = lambda: svb.svb_delta_decode(n, comp, nb, out, 0, err)
+            check = lambda: bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+        else:
+            fn = lambda: svb.svb_decode(n, comp, nb, out, err)
+            check = lambda: bool(torch.equal(out, x_dev)) and int(err.item()) == 0
+    for _ in range(warmup):
+        fl()
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        fl()
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    med = ms[len(ms) // 2]
+    ok = check()
+    print(json.dumps({"only": kind, "n": n, "steps": steps, "warmup": warmup, "median_ms": med,
+                      "uint32_per_s": n / (med * 1e-3), "ok": ok}))
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--only", choices=ONLY_KINDS, default=None,
+                    help="run one kind of call only (for profiler runs) and print its median time")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
@@ -808,6 +941,9 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        profile_only(args.only, args.steps, args.warmup)
+        return
 
     import numpy as np
     import torch
@@ -820,13 +956,15 @@ def main():
     log("generating %d document ids" % N_HEAD)
     x, _ = inputs.docids(N_HEAD, seed=2)
     x_dev = torch.from_numpy(x.view(np.int32)).cuda()
-    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
-    log("delta decode: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    r = measure_delta(svb, torch, x_dev, args.steps, args.warmup, flush_buf=flush)
+    flush_buf = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
+    flush = lambda: svb.svb_fill_u32(flush_buf.numel(), flush_buf, 0)
+    log("delta decode: %d warmup + %d timed steps (at least %d flushed reps)" % (args.warmup, args.steps, MIN_REPS))
+    r = measure_delta(svb, torch, x_dev, args.steps, args.warmup, flush)
     assert r["round_trip_ok"], "delta decode did not reproduce the input"
     dom_name = max(r["kernels_ms"], key=r["kernels_ms"].get)
     dom_ms = r["kernels_ms"][dom_name]
-    log("delta decode %.4f ms/call; dominant kernel %s %.4f ms" % (r["ms_per_call"], dom_name, dom_ms))
+    log("delta decode %.4f ms/call (flushed median); dominant kernel %s %.4f ms"
+        % (r["ms_per_call"], dom_name, dom_ms))
     copy = measure_copy(svb, torch, max(5, args.steps // 2))
     log("copy %.1f GB/s" % copy["GBps"])
 
@@ -844,7 +982,11 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N_HEAD, "compressed_bytes": r["compressed_bytes"],
-                   "bits_per_int": round(r["bits_per_int"], 4), "parallelism": "none (1 GPU)"},
+                   "bits_per_int": round(r["bits_per_int"], 4), "parallelism": "none (1 GPU)",
+                   "timing": "median of %d calls, each after a 1 GiB cache-evicting fill (HIP events)"
+                             % r["protocol"]["reps"]},
+        # the dominant kernel reads the control and data bytes and writes every integer: its
+        # algorithmic bytes are the call's
         "roofline": {"bound": "hbm", "achieved": gbs(r["alg_bytes_per_call"], dom_ms), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs(r["alg_bytes_per_call"], dom_ms) / HBM_PEAK_GBS,
                      "traffic": stored_traffic(), "kernel": dom_name, "kernel_ms": dom_ms,
@@ -852,7 +994,8 @@ def main():
                      "whole_call": {"ms": r["ms_per_call"], "GBps": r["call_GBps"],
                                     "frac": r["call_frac_of_peak"]}},
         "kernels_ms": r["kernels_ms"],
-        "flushed": r.get("flushed"),
+        "protocol": r["protocol"],
+        "unflushed": r["unflushed"],
         "encode": r["encode"],
         "copy": copy,
     }
@@ -863,23 +1006,26 @@ def main():
         x2, _ = inputs.docids(n2, seed=2)
         x2_dev = torch.from_numpy(x2.view(np.int32)).cuda()
         del x2
-        r2 = measure_delta(svb, torch, x2_dev, max(5, args.steps // 2), 2, flush_buf=flush)
+        r2 = measure_delta(svb, torch, x2_dev, MIN_REPS, 2, flush)
         assert r2["round_trip_ok"], "2^28 delta decode did not reproduce the input"
         del x2_dev
-        log("2^28 delta decode %.4f ms/call (%.1f%% of peak)" % (r2["ms_per_call"], 100 * r2["call_frac_of_peak"]))
+        log("2^28 delta decode %.4f ms/call (%.1f%% of peak, flushed median)"
+            % (r2["ms_per_call"], 100 * r2["call_frac_of_peak"]))
         line["at_2p28"] = {"delta_docids": {k: r2[k] for k in (
             "n", "compressed_bytes", "ms_per_call", "uint32_per_s", "call_GBps", "call_frac_of_peak", "kernels_ms",
-            "flushed", "encode")}}
+            "unflushed", "encode")}}
+        log("2^28 delta encode %.4f ms/call (%.1f%% of peak)"
+            % (r2["encode"]["ms_per_call"], 100 * r2["encode"]["frac_of_peak"]))
         log("generating %d stress integers" % n2)
         x3 = inputs.stress_lengths(n2, seed=3)
         x3_dev = torch.from_numpy(x3.view(np.int32)).cuda()
         del x3
-        r3 = measure_plain(svb, torch, x3_dev, max(5, args.steps // 2), 2)
+        r3 = measure_plain(svb, torch, x3_dev, MIN_REPS, 2, flush)
         assert r3["round_trip_ok"], "2^28 plain decode did not reproduce the input"
         del x3_dev
         log("2^28 plain decode %.4f ms/call (%.1f%% of peak)" % (r3["ms_per_call"], 100 * r3["call_frac_of_peak"]))
         line["at_2p28"]["plain_stress"] = r3
-    del flush
+    del flush_buf
     if not args.no_batched:
         log("batched: generating 200,000 posting lists")
         rb = measure_batched(svb, torch, np, inputs, max(5, args.steps // 2), 2, per_list=not args.no_per_list)

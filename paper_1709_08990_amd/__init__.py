@@ -26,6 +26,7 @@ __all__ = [
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
+SVB_DECODE_STALLED = 2
 SVB_BATCH_OVERFLOW = 3
 SVB_QUERY_OUT_OF_RANGE = 4
 
@@ -45,6 +46,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libsvb.so is not built (%s); run `python -m paper_1709_08990_amd.build`"
                                % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname as the system one.  Loading torch
+        # first makes libsvb.so bind to that runtime, so the process has one HIP runtime, whose
+        # device pointers and streams the tensors carry (the other one need not even see the GPU).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
         sigs = {
@@ -304,7 +309,8 @@ def svb_server_destroy(server):
 
 
 def svb_autotune_decode(n, inp, in_bytes, out, start=0, delta=False, err=None, stream=None):
-    """Times the two decoder variants on this stream; keeps and returns the faster (0 or 1)."""
+    """Times the decoder variants of this kind (plain: 0..1; delta: 0..3, bit 1 = two-pass schedule)
+    on this stream; keeps and returns the fastest."""
     v = ctypes.c_int(-1)
     _check(lib().svb_autotune_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), int(start) & 0xFFFFFFFF,
                                      int(bool(delta)), _ptr(err), ctypes.addressof(v), _stream(stream)),

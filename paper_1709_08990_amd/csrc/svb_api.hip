@@ -16,6 +16,11 @@ namespace {
 struct Workspace {
     uint8_t *scratch = nullptr;
     uint64_t scratch_bytes = 0;
+    // one-pass delta decoding: control words and one status word per group,
+    // kept apart from `scratch` (which other calls overwrite) because the
+    // kernel trusts any status word whose tag matches the running call
+    uint8_t *onepass = nullptr;
+    uint64_t onepass_groups = 0;
 };
 
 std::mutex g_mu;
@@ -81,6 +86,31 @@ int ensure_scratch(Workspace &w, uint64_t bytes, hipStream_t s) {
     return SVB_OK;
 }
 
+// The one-pass state for `groups` groups, zeroed when (re)allocated.  Caller
+// holds g_mu.
+int ensure_onepass(Workspace &w, uint64_t groups, hipStream_t s, OnePassArgs &op) {
+    if (groups > w.onepass_groups) {
+        uint64_t cap = 1ull << 10;
+        while (cap < groups) cap <<= 1;
+        if (w.onepass) {
+            if (hipStreamSynchronize(s) != hipSuccess) return SVB_ERR_HIP;
+            (void)hipFree(w.onepass);
+            w.onepass = nullptr;
+            w.onepass_groups = 0;
+        }
+        const uint64_t bytes = sizeof(OnePassCtl) + 8 * cap;
+        if (hipMalloc((void **)&w.onepass, bytes) != hipSuccess) {
+            w.onepass = nullptr;
+            return SVB_ERR_NOMEM;
+        }
+        if (launch_fill((uint32_t *)w.onepass, bytes / 4, 0u, s) != hipSuccess) return SVB_ERR_HIP;
+        w.onepass_groups = cap;
+    }
+    op.ctl = (OnePassCtl *)w.onepass;
+    op.status = (uint64_t *)(w.onepass + sizeof(OnePassCtl));
+    return SVB_OK;
+}
+
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
@@ -130,19 +160,24 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
                             [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s, seg_off32); }));
 }
 
-// Decoder variant per (device, delta): true = the zero-control variant.
-std::map<std::pair<int, int>, bool> g_zc;
+// Decoder variant per (device, delta): bit 0 = the zero-control variant,
+// bit 1 (delta only) = the two-pass schedule instead of the one-pass look-back.
+std::map<std::pair<int, int>, int> g_variant;
+constexpr int kVariantZC = 1, kVariantTwoPass = 2;
+// Polls without progress before a one-pass wave gives up (each poll is a
+// device-scope load plus a short sleep: this is on the order of a second).
+constexpr uint32_t kOnePassSpinLimit = 1u << 20;
 
-bool zc_choice(bool delta) {
+int variant_choice(bool delta) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    auto it = g_zc.find(std::make_pair(dev, delta ? 1 : 0));
-    return it != g_zc.end() && it->second;
+    auto it = g_variant.find(std::make_pair(dev, delta ? 1 : 0));
+    return it == g_variant.end() ? 0 : it->second;
 }
 
-// zc: -1 = the chosen variant for this kind of call, else 0 / 1.
+// variant: -1 = the chosen variant for this kind of call, else the bits above.
 int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
-              uint32_t *err, bool delta, void *stream, int zc_force = -1) {
+              uint32_t *err, bool delta, void *stream, int variant = -1) {
     hipStream_t s = (hipStream_t)stream;
     if (n > SVB_MAX_N) return SVB_ERR_INVALID;
     if (err && !aligned4(err)) return SVB_ERR_INVALID;
@@ -160,11 +195,15 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     const uint64_t o_scan = o_gvpre + up16(4 * groups);
     const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
     std::lock_guard<std::mutex> lock(g_mu);
-    const bool zc = zc_force < 0 ? zc_choice(delta) : zc_force != 0;
+    const int var = variant < 0 ? variant_choice(delta) : variant;
+    const bool zc = (var & kVariantZC) != 0;
+    const bool two_pass = delta && (var & kVariantTwoPass) != 0;
     Workspace *w;
     int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
     if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
+    OnePassArgs op = {};
+    if (delta && !two_pass && (st = ensure_onepass(*w, groups, s, op)) != SVB_OK) return st;
     uint8_t *sc = w->scratch;
 
     // data-stream offset of every group (and segment), from the control stream
@@ -195,6 +234,12 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     a.goff = (const uint64_t *)(sc + o_goff);
     a.gvsum = (uint32_t *)(sc + o_gvsum);
     a.gvpre = (const uint32_t *)(sc + o_gvpre);
+    if (delta && !two_pass) {
+        op.start = start;
+        op.spin_limit = kOnePassSpinLimit;
+        return hip_status(
+            timed("decode_delta_onepass", s, [&] { return launch_delta_onepass(a, goff32, op, zc, s); }));
+    }
     if (delta) {
         // value sum of every group, then start + their exclusive prefix
         if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s, zc, goff32); }))) !=
@@ -210,9 +255,10 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
               [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc, goff32); }));
 }
 
-// Times the two decoder variants on the caller's stream (median of five
-// calls after two untimed ones each) and keeps the faster for this kind of
-// call on the current device.
+// Times the decoder variants (plain: general and zero-control; delta: those
+// two under each schedule) on the caller's stream, median of five calls after
+// two untimed ones each, and keeps the fastest for this kind of call on the
+// current device.
 int autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, uint32_t *err,
                     bool delta, int *chosen, void *stream) {
     hipStream_t s = (hipStream_t)stream;
@@ -222,9 +268,10 @@ int autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *
         (void)hipEventDestroy(e0);
         return SVB_ERR_HIP;
     }
-    float best_ms[2] = {1e30f, 1e30f};
+    const int nvar = delta ? 4 : 2;
+    float best_ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
     int st = SVB_OK;
-    for (int v = 0; v < 2 && st == SVB_OK; ++v) {
+    for (int v = 0; v < nvar && st == SVB_OK; ++v) {
         for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_decode(n, in, in_bytes, out, start, err, delta, stream, v);
         constexpr int kReps = 5;
         float times[kReps];
@@ -243,14 +290,16 @@ int autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SVB_OK) return st;
-    const bool zc = best_ms[1] < best_ms[0];
+    int best = 0;
+    for (int v = 1; v < nvar; ++v)
+        if (best_ms[v] < best_ms[best]) best = v;
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        g_zc[std::make_pair(dev, delta ? 1 : 0)] = zc;
+        g_variant[std::make_pair(dev, delta ? 1 : 0)] = best;
     }
-    if (chosen) *chosen = zc ? 1 : 0;
+    if (chosen) *chosen = best;
     return SVB_OK;
 }
 
@@ -729,11 +778,11 @@ int svb_autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32
 }
 
 int svb_set_decode_variant(int delta, int variant) {
-    if (variant != 0 && variant != 1) return SVB_ERR_INVALID;
+    if (variant < 0 || variant > (delta ? 3 : 1)) return SVB_ERR_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
     std::lock_guard<std::mutex> lock(g_mu);
-    g_zc[std::make_pair(dev, delta ? 1 : 0)] = variant == 1;
+    g_variant[std::make_pair(dev, delta ? 1 : 0)] = variant;
     return SVB_OK;
 }
 
@@ -817,6 +866,7 @@ void svb_release_workspace(void) {
         (void)hipSetDevice(kv.first.first);
         (void)hipDeviceSynchronize();
         if (kv.second.scratch) (void)hipFree(kv.second.scratch);
+        if (kv.second.onepass) (void)hipFree(kv.second.onepass);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);

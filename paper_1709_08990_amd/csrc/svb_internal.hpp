@@ -59,6 +59,25 @@ hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uin
 hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false,
                          const uint32_t *goff32 = nullptr);
 
+// One-pass delta decoding (svb_delta.hip): a chained scan over the groups'
+// value sums with a decoupled look-back.  The state lives in device memory
+// that only this kernel touches; it must be zeroed once when allocated and is
+// left ready for the next call by the kernel itself.
+struct OnePassCtl {
+    uint32_t ticket;  // workgroups that have started the running call
+    uint32_t done;    // workgroups that have finished it
+    uint32_t epoch;   // call counter (mod 2^31 - 1), part of every status tag
+    uint32_t pad;
+};
+struct OnePassArgs {
+    uint64_t *status;  // per group: tag (epoch << 1 | inclusive) << 32 | value
+    OnePassCtl *ctl;
+    uint32_t start;
+    uint32_t spin_limit;  // polls without progress before a wave gives up (SVB_DECODE_STALLED)
+};
+hipError_t launch_delta_onepass(const DecodeArgs &a, const uint32_t *goff32, const OnePassArgs &op, bool zc,
+                                hipStream_t s);
+
 // Batched calls.  A task is one 1024-integer segment of one list; each wave of
 // the main pass takes `chunk` consecutive tasks.
 //

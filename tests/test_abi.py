@@ -89,7 +89,8 @@ def test_comparison_format_sizes_and_argument_errors():
 
 
 def test_decoder_variant_is_checked():
-    assert svb.lib().svb_set_decode_variant(1, 2) == -1
+    assert svb.lib().svb_set_decode_variant(1, 4) == -1
+    assert svb.lib().svb_set_decode_variant(0, 2) == -1
 
 
 def test_bench_refuses_more_than_one_gpu():
