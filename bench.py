@@ -563,7 +563,7 @@ def measure_zero_control(svb, torch, np, steps, warmup, n=1 << 28):
         res["variant%d" % v] = {"ms_per_call": ms, "uint32_per_s": n / (ms * 1e-3),
                                 "call_frac_of_peak": gbs(nb + 4 * n, ms) / HBM_PEAK_GBS, "kernels_ms": kms,
                                 "round_trip_ok": bool(torch.equal(out, x_dev))}
-    svb.svb_set_decode_variant(True, 0)
+    svb.svb_set_decode_variant(True, -1)
     res["speedup"] = res["variant0"]["ms_per_call"] / res["variant1"]["ms_per_call"]
     del x_dev, comp, out
     return res
@@ -822,7 +822,7 @@ def run_cpu_baseline(x, min_seconds=10.0):
 ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched")
 
 
-def profile_only(kind, steps, warmup):
+def profile_only(kind, steps, warmup, variant=None):
     """Runs one kind of call only (`warmup` + `steps` calls, each after the 1 GiB cache-evicting
     fill), for rocprofv3 runs that should see nothing else: delta26 / delta28 (delta decode of the
     document ids at 2^26 / 2^28), plain28 (plain decode of 2^28 integers of unpredictable length),
@@ -836,6 +836,8 @@ def profile_only(kind, steps, warmup):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     svb.lib()
+    if variant is not None:
+        svb.svb_set_decode_variant(kind != "plain28", variant)
     flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
     fl = lambda: svb.svb_fill_u32(flush.numel(), flush, 0)
     if kind == "batched":
@@ -895,7 +897,7 @@ def profile_only(kind, steps, warmup):
     ms = sorted(a.elapsed_time(b) for a, b in ev)
     med = ms[len(ms) // 2]
     ok = check()
-    print(json.dumps({"only": kind, "n": n, "steps": steps, "warmup": warmup, "median_ms": med,
+    print(json.dumps({"only": kind, "variant": variant, "n": n, "steps": steps, "warmup": warmup, "median_ms": med,
                       "uint32_per_s": n / (med * 1e-3), "ok": ok}))
     if not ok:
         sys.exit(1)
@@ -905,6 +907,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--only", choices=ONLY_KINDS, default=None,
                     help="run one kind of call only (for profiler runs) and print its median time")
+    ap.add_argument("--decode-variant", type=int, default=None,
+                    help="with --only: the decoder variant to set first (svb_set_decode_variant)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
@@ -942,7 +946,7 @@ def main():
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.only:
-        profile_only(args.only, args.steps, args.warmup)
+        profile_only(args.only, args.steps, args.warmup, args.decode_variant)
         return
 
     import numpy as np

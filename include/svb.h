@@ -61,11 +61,8 @@ enum svb_status {
  * control bytes describe more data than in_bytes holds. */
 #define SVB_DECODE_CORRUPT 1u
 
-/* Value the one-pass delta decoder writes to `err` if a wave gave up waiting
- * for the running sum of the groups before its own (a bounded wait of about
- * a second; it is not expected to happen).  The output is then unspecified;
- * every kernel still ends. */
-#define SVB_DECODE_STALLED 2u
+/* (Value 2 is not used: no kernel of the library waits for another
+ * workgroup, so none can stall.) */
 
 /* Value a batched decode writes to `err` when the lists hold more integers
  * than the caller's total_ints bound (nothing is decoded then). */
@@ -125,15 +122,12 @@ int svb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, 
                void *stream);
 
 /* svb_delta_decode -- svb_decode followed by the running sum modulo 2^32
- * starting from `start` (Section 2, "Differential Coding"; Section 5), fused
- * into the decoding pass.  By default the stream is read once: every group of
- * 4096 integers sums its own differences without decoding them, takes the sum
- * of all groups before it from a chained scan (a look-back over per-group
- * status words), then decodes.  The status words and a ticket counter live in
- * library-owned device memory per (device, stream), which the kernel leaves
- * ready for the next call; calls on one stream are ordered, so they never
- * share it.  svb_set_decode_variant selects the two-pass schedule instead
- * (sums, scan, decode).  err may also receive SVB_DECODE_STALLED. */
+ * starting from `start` (Section 2, "Differential Coding"; Section 5).  Each
+ * group of 4096 integers first has its sum of stored differences taken (its
+ * plain byte sum plus a correction per block of multi-byte integers, or by
+ * decoding it, see the decoder variants), the sums are scanned from `start`,
+ * then every group decodes from its carry with the running sum fused into the
+ * decode. */
 int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out,
                      uint32_t start, uint32_t *err, void *stream);
 
@@ -289,17 +283,19 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
  * decoder; 1 = also decode every row of 64 blocks whose control bytes are all
  * zero (256 one-byte integers) by widening bytes, which pays only where such
  * rows are common (small deltas everywhere) and costs a test per row
- * elsewhere.  Bit 1, delta decoding only (the scan schedule of the running
- * sum, Section 2): 0 = one pass over the stream with a chained look-back
- * across groups; 1 = two passes (every group's sum of differences, a scan,
- * then the decode).  Plain decoding takes variants 0..1, delta decoding
+ * elsewhere.  Bit 1, delta decoding only (how each group's sum of stored
+ * differences is taken before the running sum, Section 2): 0 = from the
+ * group's plain byte sum plus a correction per block of multi-byte integers;
+ * 1 = by decoding the group.  Plain decoding takes variants 0..1, delta decoding
  * 0..3.  svb_autotune_decode times every variant of the kind on the caller's
  * stream (the arguments of svb_decode / svb_delta_decode; it decodes several
  * times and synchronises the stream), keeps the fastest for later calls of
  * that kind (plain or delta) on the current device and writes it to
- * *variant; svb_set_decode_variant sets it directly (SVB_ERR_INVALID for a
- * variant out of range).  All variants give identical output.  The default
- * is 0.
+ * *variant; svb_set_decode_variant sets it directly (-1: back to the
+ * automatic choice below; SVB_ERR_INVALID for a variant out of range).  All variants give identical output.  Until one is
+ * tuned or set, the general decoder is used, and delta decoding takes the sums
+ * from byte sums unless the stream averages more than 4480 data bytes per
+ * group (about 1.1 bytes per integer), where it decodes them.
  */
 int svb_autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, int delta,
                         uint32_t *err, int *variant, void *stream);

@@ -26,7 +26,6 @@ __all__ = [
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsvb.so")
 SVB_DECODE_CORRUPT = 1
-SVB_DECODE_STALLED = 2
 SVB_BATCH_OVERFLOW = 3
 SVB_QUERY_OUT_OF_RANGE = 4
 
@@ -173,24 +172,36 @@ def svb_delta_decode(n, inp, in_bytes, out, start=0, err=None, stream=None):
                   "svb_delta_decode")
 
 
-def svb_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=0,
+def _total_ints(total_ints):
+    """The batched calls size their task table from total_ints, an upper bound on the integers of
+    all lists: with 0 every list must fit one 1024-integer segment, and a longer one makes the call
+    do nothing but flag SVB_BATCH_OVERFLOW.  So the binding asks for the bound explicitly."""
+    if total_ints is None:
+        raise ValueError("total_ints is required: an upper bound on the integers of all lists")
+    return int(total_ints)
+
+
+def svb_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=None,
                      stream=None):
+    total_ints = _total_ints(total_ints)
     return _check(lib().svb_encode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(inp), _ptr(out_off),
                                          _ptr(out), _ptr(out_bytes), _ptr(starts), int(total_ints),
                                          _stream(stream)), "svb_encode_batch")
 
 
-def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=0, err=None,
+def svb_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=None, err=None,
                      stream=None):
+    total_ints = _total_ints(total_ints)
     return _check(lib().svb_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
                                          _ptr(out_off), _ptr(out), _ptr(starts), int(total_ints), _ptr(err),
                                          _stream(stream)), "svb_decode_batch")
 
 
-def svb_autotune_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=0,
+def svb_autotune_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, starts=None, total_ints=None,
                               err=None, stream=None):
     """Times each chunk choice (consecutive tasks per wave) on this batch, keeps the fastest for
     later calls of this kind; returns it."""
+    total_ints = _total_ints(total_ints)
     chosen = ctypes.c_uint32(0)
     _check(lib().svb_autotune_decode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(in_bytes), _ptr(inp),
                                            _ptr(out_off), _ptr(out), _ptr(starts), int(total_ints), _ptr(err),
@@ -198,8 +209,9 @@ def svb_autotune_decode_batch(m, counts, in_off, in_bytes, inp, out_off, out, st
     return int(chosen.value)
 
 
-def svb_autotune_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=0,
+def svb_autotune_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=None, starts=None, total_ints=None,
                               stream=None):
+    total_ints = _total_ints(total_ints)
     chosen = ctypes.c_uint32(0)
     _check(lib().svb_autotune_encode_batch(int(m), _ptr(counts), _ptr(in_off), _ptr(inp), _ptr(out_off),
                                            _ptr(out), _ptr(out_bytes), _ptr(starts), int(total_ints),
@@ -309,8 +321,8 @@ def svb_server_destroy(server):
 
 
 def svb_autotune_decode(n, inp, in_bytes, out, start=0, delta=False, err=None, stream=None):
-    """Times the decoder variants of this kind (plain: 0..1; delta: 0..3, bit 1 = two-pass schedule)
-    on this stream; keeps and returns the fastest."""
+    """Times the decoder variants of this kind (plain: 0..1; delta: 0..3, bit 1 = value sums by
+    decoding) on this stream; keeps and returns the fastest."""
     v = ctypes.c_int(-1)
     _check(lib().svb_autotune_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out), int(start) & 0xFFFFFFFF,
                                      int(bool(delta)), _ptr(err), ctypes.addressof(v), _stream(stream)),

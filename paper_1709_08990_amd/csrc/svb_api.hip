@@ -16,11 +16,6 @@ namespace {
 struct Workspace {
     uint8_t *scratch = nullptr;
     uint64_t scratch_bytes = 0;
-    // one-pass delta decoding: control words and one status word per group,
-    // kept apart from `scratch` (which other calls overwrite) because the
-    // kernel trusts any status word whose tag matches the running call
-    uint8_t *onepass = nullptr;
-    uint64_t onepass_groups = 0;
 };
 
 std::mutex g_mu;
@@ -86,31 +81,6 @@ int ensure_scratch(Workspace &w, uint64_t bytes, hipStream_t s) {
     return SVB_OK;
 }
 
-// The one-pass state for `groups` groups, zeroed when (re)allocated.  Caller
-// holds g_mu.
-int ensure_onepass(Workspace &w, uint64_t groups, hipStream_t s, OnePassArgs &op) {
-    if (groups > w.onepass_groups) {
-        uint64_t cap = 1ull << 10;
-        while (cap < groups) cap <<= 1;
-        if (w.onepass) {
-            if (hipStreamSynchronize(s) != hipSuccess) return SVB_ERR_HIP;
-            (void)hipFree(w.onepass);
-            w.onepass = nullptr;
-            w.onepass_groups = 0;
-        }
-        const uint64_t bytes = sizeof(OnePassCtl) + 8 * cap;
-        if (hipMalloc((void **)&w.onepass, bytes) != hipSuccess) {
-            w.onepass = nullptr;
-            return SVB_ERR_NOMEM;
-        }
-        if (launch_fill((uint32_t *)w.onepass, bytes / 4, 0u, s) != hipSuccess) return SVB_ERR_HIP;
-        w.onepass_groups = cap;
-    }
-    op.ctl = (OnePassCtl *)w.onepass;
-    op.status = (uint64_t *)(w.onepass + sizeof(OnePassCtl));
-    return SVB_OK;
-}
-
 bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
@@ -160,19 +130,21 @@ int do_encode(uint64_t n, const uint32_t *in, uint8_t *out, uint32_t start, uint
                             [&] { return launch_encode_pack(e, delta, seg_off, segs, out_bytes, s, seg_off32); }));
 }
 
-// Decoder variant per (device, delta): bit 0 = the zero-control variant,
-// bit 1 (delta only) = the two-pass schedule instead of the one-pass look-back.
+// Decoder variant per (device, delta), once tuned or set: bit 0 = the
+// zero-control variant; bit 1 (delta only) = the value sums by decoding each
+// group instead of from its byte sum and corrections.  Unset: the general
+// decoder, and for delta decoding the value sums chosen from the stream's mean
+// bytes per group (byte sums where a group's span usually fits the staging
+// area of the value-sum kernel, decoding above).
 std::map<std::pair<int, int>, int> g_variant;
-constexpr int kVariantZC = 1, kVariantTwoPass = 2;
-// Polls without progress before a one-pass wave gives up (each poll is a
-// device-scope load plus a short sleep: this is on the order of a second).
-constexpr uint32_t kOnePassSpinLimit = 1u << 20;
+constexpr int kVariantZC = 1, kVariantSumsByDecoding = 2;
+constexpr uint64_t kByteSumsMaxSpan = 4480;  // mean data bytes per group (staging area 4608)
 
 int variant_choice(bool delta) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto it = g_variant.find(std::make_pair(dev, delta ? 1 : 0));
-    return it == g_variant.end() ? 0 : it->second;
+    return it == g_variant.end() ? -1 : it->second;
 }
 
 // variant: -1 = the chosen variant for this kind of call, else the bits above.
@@ -190,20 +162,19 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
     const uint64_t o_gbytes = 0;
     const uint64_t o_goff = o_gbytes + up16(4 * groups);
-    const uint64_t o_gvsum = o_goff + up16(8 * groups);
+    const uint64_t o_gvsum = o_goff + up16(8 * (groups + 1));
     const uint64_t o_gvpre = o_gvsum + up16(4 * groups);
     const uint64_t o_scan = o_gvpre + up16(4 * groups);
     const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
     std::lock_guard<std::mutex> lock(g_mu);
-    const int var = variant < 0 ? variant_choice(delta) : variant;
-    const bool zc = (var & kVariantZC) != 0;
-    const bool two_pass = delta && (var & kVariantTwoPass) != 0;
+    const int chosen = variant < 0 ? variant_choice(delta) : variant;
+    const bool zc = chosen > 0 && (chosen & kVariantZC) != 0;
+    const bool sums_by_decoding = chosen < 0 ? (in_bytes - (n + 3) / 4) / groups > kByteSumsMaxSpan
+                                             : (chosen & kVariantSumsByDecoding) != 0;
     Workspace *w;
     int st = acquire_locked(s, &w);
     if (st != SVB_OK) return st;
     if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
-    OnePassArgs op = {};
-    if (delta && !two_pass && (st = ensure_onepass(*w, groups, s, op)) != SVB_OK) return st;
     uint8_t *sc = w->scratch;
 
     // data-stream offset of every group (and segment), from the control stream
@@ -213,13 +184,15 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     ga.n = n;
     ga.groups = groups;
     ga.gbytes = (uint32_t *)(sc + o_gbytes);
-    ga.seg_loc = nullptr;
     if ((st = hip_status(timed("group_bytes", s, [&] { return launch_group_bytes(ga, s); }))) != SVB_OK) return st;
     // offsets below 2^32 (a data stream under 4 GiB) scan in 32 bits: half
     // the bytes written and read
     const bool off32 = in_bytes < (1ull << 32);
+    // the total lands after the last group's offset (the value-sum pass reads
+    // each group's end)
+    void *goff_end = off32 ? (void *)((uint32_t *)(sc + o_goff) + groups) : (void *)((uint64_t *)(sc + o_goff) + groups);
     if ((st = hip_status(timed("scan_offsets", s, [&] {
-             return launch_scan(ga.gbytes, sc + o_goff, groups, !off32, 0u, s, nullptr, sc + o_scan);
+             return launch_scan(ga.gbytes, sc + o_goff, groups, !off32, 0u, s, goff_end, sc + o_scan);
          }))) != SVB_OK)
         return st;
     const uint32_t *goff32 = off32 ? (const uint32_t *)(sc + o_goff) : nullptr;
@@ -234,16 +207,11 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     a.goff = (const uint64_t *)(sc + o_goff);
     a.gvsum = (uint32_t *)(sc + o_gvsum);
     a.gvpre = (const uint32_t *)(sc + o_gvpre);
-    if (delta && !two_pass) {
-        op.start = start;
-        op.spin_limit = kOnePassSpinLimit;
-        return hip_status(
-            timed("decode_delta_onepass", s, [&] { return launch_delta_onepass(a, goff32, op, zc, s); }));
-    }
     if (delta) {
         // value sum of every group, then start + their exclusive prefix
-        if ((st = hip_status(timed("group_sums", s, [&] { return launch_decode(a, kSums, s, zc, goff32); }))) !=
-            SVB_OK)
+        if ((st = hip_status(timed("group_sums", s, [&] {
+                 return sums_by_decoding ? launch_decode(a, kSums, s, zc, goff32) : launch_group_sums(a, goff32, s);
+             }))) != SVB_OK)
             return st;
         if ((st = hip_status(timed("scan_sums", s, [&] {
                  return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s, nullptr, sc + o_scan);
@@ -256,9 +224,9 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
 }
 
 // Times the decoder variants (plain: general and zero-control; delta: those
-// two under each schedule) on the caller's stream, median of five calls after
-// two untimed ones each, and keeps the fastest for this kind of call on the
-// current device.
+// two with each way of taking the value sums) on the caller's stream, median
+// of five calls after two untimed ones each, and keeps the fastest for this
+// kind of call on the current device.
 int autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, uint32_t *err,
                     bool delta, int *chosen, void *stream) {
     hipStream_t s = (hipStream_t)stream;
@@ -778,11 +746,14 @@ int svb_autotune_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32
 }
 
 int svb_set_decode_variant(int delta, int variant) {
-    if (variant < 0 || variant > (delta ? 3 : 1)) return SVB_ERR_INVALID;
+    if (variant < -1 || variant > (delta ? 3 : 1)) return SVB_ERR_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
     std::lock_guard<std::mutex> lock(g_mu);
-    g_variant[std::make_pair(dev, delta ? 1 : 0)] = variant;
+    if (variant < 0)
+        g_variant.erase(std::make_pair(dev, delta ? 1 : 0));
+    else
+        g_variant[std::make_pair(dev, delta ? 1 : 0)] = variant;
     return SVB_OK;
 }
 
@@ -866,7 +837,6 @@ void svb_release_workspace(void) {
         (void)hipSetDevice(kv.first.first);
         (void)hipDeviceSynchronize();
         if (kv.second.scratch) (void)hipFree(kv.second.scratch);
-        if (kv.second.onepass) (void)hipFree(kv.second.onepass);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);

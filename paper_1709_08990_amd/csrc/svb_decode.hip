@@ -7,16 +7,17 @@
 // 2) adds a running sum on top.  Both the pointer advance and the running sum
 // are prefix sums, so here they become scans:
 //
-//   1. group_bytes_kernel: data bytes of every group (kGroupInts integers)
-//      and each segment's byte offset inside its group, from the control
-//      stream alone: 4 integers per control byte plus the sum of its codes;
+//   1. group_bytes_kernel: data bytes of every group (kGroupInts integers),
+//      from the control stream alone: 4 integers per control byte plus the
+//      sum of its codes;
 //   2. a device scan (svb_scan.hip) of the group byte counts -> each group's
 //      offset in the data stream;
 //   3. decode_kernel: one wave per group walks its segments (1024 integers =
 //      256 control bytes each) in order.  Plain decoding stores the integers.
-//      Delta decoding runs it twice: first summing each group's stored
-//      differences (nothing stored), then -- after a scan of those sums
-//      modulo 2^32 from `start` -- storing the running sum.
+//      Delta decoding first needs each group's sum of stored differences
+//      (svb_delta.hip takes it without decoding; the kSums mode below takes
+//      it by decoding, for dense streams), then -- after a scan of those sums
+//      modulo 2^32 from `start` -- stores the running sum.
 //
 // Inside a segment, lane l owns control bytes l, l + 64, l + 128, l + 192, so
 // each of its four store instructions writes 64 consecutive 16-byte slots.
@@ -33,23 +34,63 @@
 namespace svb {
 
 // --------------------------------------------------------------------------
-// 1. data bytes per group (and, on request, each segment's byte offset inside
-// its group)
+// 1. data bytes per group
+
+// kBytesGroups groups per wave, lane l reading control bytes 16 l .. 16 l + 15
+// of each (one 16-byte load and, when the stream is not 4-byte aligned, one
+// more dword): every load of the wave is issued before any is used, so a wave
+// keeps kBytesGroups KiB in flight.  Each control byte stands for 4 integers
+// plus the sum of its codes (Section 4).
+#ifndef SVB_BYTES_GROUPS
+#define SVB_BYTES_GROUPS 1  // measured at 2^28: 1, 2, 4 groups per wave 0.398, 0.401, 0.403 ms per delta call
+#endif
+constexpr uint32_t kBytesGroups = SVB_BYTES_GROUPS;
+static_assert(kGroupCtrl == 16 * kWave, "16 control bytes per lane and group");
 
 __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p) {
-    constexpr uint32_t kPerLane = kGroupCtrl / kWave;      // control bytes per lane
-    constexpr uint32_t kLanesPerSeg = kSegCtrl / kPerLane;  // lanes covering one segment
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-    const uint64_t g = (uint64_t)blockIdx.x * kWaves + wave;
-    if (g >= p.groups) return;
-    const uint32_t bytes = lane_ctrl_bytes<kPerLane>(p.in, p.in_bytes, p.n, g * kGroupCtrl, lane);
-    const uint32_t incl = wave_incl_scan(bytes);
-    if (p.seg_loc && (lane % kLanesPerSeg) == 0) {
-        const uint64_t s = g * kGroupSegs + lane / kLanesPerSeg;
-        if (s * kSegInts < p.n) p.seg_loc[s] = incl - bytes;
+    const uint64_t g0 = ((uint64_t)blockIdx.x * kWaves + wave) * kBytesGroups;
+    if (g0 >= p.groups) return;
+    const uint64_t full = p.n / kGroupInts;  // groups whose 1024 control bytes all lie below ceil(n/4)
+    uint32_t x[kBytesGroups][4];
+#pragma unroll
+    for (uint32_t k = 0; k < kBytesGroups; ++k) {
+        const uint64_t g = g0 + k;
+        if (g >= full) break;  // wave-uniform
+        const uint8_t *cp = p.in + g * kGroupCtrl + 16ull * lane;
+        const uint32_t sh = (uint32_t)((uintptr_t)cp & 3u);
+        const uint32_t *ap = (const uint32_t *)(cp - sh);
+        const u32x4 w = *gptr((const u32x4 *)ap);
+        const uint32_t w4 = sh ? gptr(ap)[4] : 0u;
+        x[k][0] = __builtin_amdgcn_alignbyte(w.y, w.x, sh);
+        x[k][1] = __builtin_amdgcn_alignbyte(w.z, w.y, sh);
+        x[k][2] = __builtin_amdgcn_alignbyte(w.w, w.z, sh);
+        x[k][3] = __builtin_amdgcn_alignbyte(w4, w.w, sh);
     }
-    if (lane == kWave - 1) p.gbytes[g] = incl;
+#pragma unroll
+    for (uint32_t k = 0; k < kBytesGroups; ++k) {
+        const uint64_t g = g0 + k;
+        if (g >= p.groups) break;  // wave-uniform
+        uint32_t bytes;
+        if (g < full) {
+            uint32_t codes = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) codes += __builtin_popcount(x[k][i]) + __builtin_popcount(x[k][i] & 0xAAAAAAAAu);
+            bytes = 64u + codes;
+        } else {
+            // the stream's last, partial group: byte loads, integers past n not counted
+            const uint64_t nblocks = (p.n + 3) >> 2;
+            const uint32_t last_r = (p.n & 3) ? (uint32_t)(p.n & 3) : 4u;
+            bytes = 0;
+            for (uint32_t i = 0; i < 16; ++i) {
+                const uint64_t b = g * kGroupCtrl + 16ull * lane + i;
+                if (b < nblocks) bytes += control_data_bytes(gptr(p.in)[b], b == nblocks - 1 ? last_r : 4u);
+            }
+        }
+        const uint32_t tot = wave_last(wave_incl_scan(bytes));
+        if (lane == 0) p.gbytes[g] = tot;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -101,7 +142,8 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const ui
 // launchers
 
 hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s) {
-    const uint64_t grid = (a.groups + kWaves - 1) / kWaves;
+    const uint64_t waves = (a.groups + kBytesGroups - 1) / kBytesGroups;
+    const uint64_t grid = (waves + kWaves - 1) / kWaves;
     hipLaunchKernelGGL(group_bytes_kernel, dim3((uint32_t)grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }

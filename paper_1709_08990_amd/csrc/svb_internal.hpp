@@ -28,7 +28,6 @@ struct GroupBytesArgs {
     uint64_t n;
     uint64_t groups;
     uint32_t *gbytes;      // out: data bytes of each group
-    uint32_t *seg_loc;     // out (may be null): byte offset of each segment inside its group
 };
 
 struct DecodeArgs {
@@ -59,24 +58,11 @@ hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uin
 hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false,
                          const uint32_t *goff32 = nullptr);
 
-// One-pass delta decoding (svb_delta.hip): a chained scan over the groups'
-// value sums with a decoupled look-back.  The state lives in device memory
-// that only this kernel touches; it must be zeroed once when allocated and is
-// left ready for the next call by the kernel itself.
-struct OnePassCtl {
-    uint32_t ticket;  // workgroups that have started the running call
-    uint32_t done;    // workgroups that have finished it
-    uint32_t epoch;   // call counter (mod 2^31 - 1), part of every status tag
-    uint32_t pad;
-};
-struct OnePassArgs {
-    uint64_t *status;  // per group: tag (epoch << 1 | inclusive) << 32 | value
-    OnePassCtl *ctl;
-    uint32_t start;
-    uint32_t spin_limit;  // polls without progress before a wave gives up (SVB_DECODE_STALLED)
-};
-hipError_t launch_delta_onepass(const DecodeArgs &a, const uint32_t *goff32, const OnePassArgs &op, bool zc,
-                                hipStream_t s);
+// Delta decoding's value sums (gvsum per group) without decoding: the plain sum
+// of each group's data bytes plus a correction per block whose control byte is
+// not zero (svb_delta.hip).  Reads the group offsets and the total after them
+// (goff[groups]).
+hipError_t launch_group_sums(const DecodeArgs &a, const uint32_t *goff32, hipStream_t s);
 
 // Batched calls.  A task is one 1024-integer segment of one list; each wave of
 // the main pass takes `chunk` consecutive tasks.

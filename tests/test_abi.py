@@ -91,6 +91,7 @@ def test_comparison_format_sizes_and_argument_errors():
 def test_decoder_variant_is_checked():
     assert svb.lib().svb_set_decode_variant(1, 4) == -1
     assert svb.lib().svb_set_decode_variant(0, 2) == -1
+    assert svb.lib().svb_set_decode_variant(1, -2) == -1
 
 
 def test_bench_refuses_more_than_one_gpu():
@@ -99,3 +100,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_batched_bindings_require_the_integer_bound():
+    """Without total_ints the task table would be sized for lists of one segment each; the binding
+    refuses the call before it reaches the library."""
+    import pytest
+    for f, args in ((svb.svb_decode_batch, (1, 0, 0, 0, 0, 0, 0)), (svb.svb_encode_batch, (1, 0, 0, 0, 0, 0)),
+                    (svb.svb_autotune_decode_batch, (1, 0, 0, 0, 0, 0, 0)),
+                    (svb.svb_autotune_encode_batch, (1, 0, 0, 0, 0, 0))):
+        with pytest.raises(ValueError):
+            f(*args)

@@ -1,13 +1,14 @@
-"""GPU parity of the two delta-decoding schedules, through the C ABI, against the oracle.
+"""GPU parity of the delta decoder's two ways of taking the value sums, through the C ABI, against
+the oracle.
 
 Delta decoding needs, for every group of integers, the sum of all differences stored before it.
-Variant bit 1 clear: one pass over the stream, each group's sum taken without decoding it (plain
-byte sum plus per-block corrections) and chained across groups by a look-back.  Bit 1 set: two
-passes (sums, scan, decode).  Bit 0 picks the zero-control decoder.  All four must equal the
-oracle exactly, on streams of every shape the one-pass sum treats differently: one-byte
-differences (no corrections), every length (corrections on nearly every block), partial last
-groups and blocks, byte misalignment, corrupt streams, and calls of changing sizes in a row (the
-look-back's status words are reused from call to call without clearing).
+Variant bit 1 clear: each group's sum from its plain byte sum plus a correction per block of
+multi-byte integers, read from the span staged in LDS (or, past the staged part, from memory).
+Bit 1 set: each group's sum by decoding it.  Bit 0 picks the zero-control decoder.  All four, and
+the automatic choice, must equal the oracle exactly, on streams of every shape the byte sum treats
+differently: one-byte differences (no corrections), every length (corrections on nearly every
+block, spans past the staged part), partial last groups and blocks, byte misalignment, corrupt
+streams, and calls of changing sizes in a row.
 """
 import numpy as np
 import pytest
@@ -22,7 +23,7 @@ torch = pytest.importorskip("torch")
 svb = pytest.importorskip("paper_1709_08990_amd")
 
 GROUP = 4096
-VARIANTS = [0, 1, 2, 3]
+VARIANTS = [-1, 0, 1, 2, 3]  # -1: the automatic choice
 SIZES = [1, 2, 3, 4, 5, 63, 64, 65, 1023, 1024, 1025, GROUP - 1, GROUP, GROUP + 1, 2 * GROUP + 3,
          5 * GROUP - 2, 64 * GROUP + 7, 257 * GROUP + 1, 250_001]
 
@@ -33,11 +34,11 @@ def _device():
     svb.lib()
     yield
     torch.cuda.synchronize()
-    svb.svb_set_decode_variant(True, 0)
+    svb.svb_set_decode_variant(True, -1)
 
 
 def kinds(n, seed):
-    """Value arrays whose delta streams differ in what the one-pass sum does with them."""
+    """Value arrays whose delta streams differ in what the byte sum does with them."""
     rng = np.random.default_rng(seed)
     docids, _ = inputs.docids(n, seed=seed, start=int(rng.integers(0, 1 << 32)))
     every_len = np.cumsum(inputs.stress_lengths(n, seed=seed), dtype=np.uint32)
@@ -74,7 +75,7 @@ def test_schedules_match_oracle(n, variant):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_random_streams_with_garbage_tail_codes(variant):
     """Random control bytes (garbage in the unused codes of the last block) and random data: the
-    one-pass corrections see blocks of every length pattern, partial last blocks included."""
+    corrections see blocks of every length pattern, partial last blocks included."""
     for n in (1, 2, 3, 5, 6, 7, 4097, 4098, 4099, 3 * GROUP + 1, 40_003):
         k = (n + 3) // 4
         ctrl = inputs.random_bytes(k, seed=500 + n)
@@ -101,10 +102,10 @@ def test_truncated_streams_flag_corrupt(variant):
             assert err == svb.SVB_DECODE_CORRUPT
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [-1, 0, 2])
 def test_calls_of_changing_size_in_a_row(variant):
-    """The look-back's status words and ticket live across calls: large, small, large again, with
-    different starts, on one stream and on a second one, each checked."""
+    """The library's scratch lives across calls: large, small, large again, with different starts,
+    on one stream and on a second one, each checked."""
     sizes = [300 * GROUP + 5, 3, GROUP + 1, 100 * GROUP, 1, 300 * GROUP + 5, 17 * GROUP - 1]
     xs = [inputs.docids(n, seed=70 + i, start=i * 1_000_003)[0] for i, n in enumerate(sizes)]
     refs = [oracle.encode(x, delta=True, start=i * 7) for i, x in enumerate(xs)]
@@ -125,13 +126,12 @@ def test_calls_of_changing_size_in_a_row(variant):
             np.testing.assert_array_equal(u32_host(o), x)
 
 
-def test_many_calls_reuse_the_state():
-    """200 one-pass calls in a row on one stream, sizes cycling, the last of each size checked, and
-    the two schedules giving the same words."""
+def test_many_calls_reuse_the_scratch():
+    """200 calls in a row on one stream, sizes cycling, the last of each size checked."""
     xs = [inputs.docids(n, seed=90 + n, start=n)[0] for n in (GROUP * 9 + 1, 77, GROUP * 33)]
     refs = [to_dev_u8(oracle.encode(x, delta=True, start=5)) for x in xs]
     outs = [torch.empty(x.size, dtype=torch.int32, device="cuda") for x in xs]
-    svb.svb_set_decode_variant(True, 0)
+    svb.svb_set_decode_variant(True, -1)
     log_case("delta many calls")
     for k in range(200):
         i = k % 3
@@ -139,3 +139,18 @@ def test_many_calls_reuse_the_state():
     torch.cuda.synchronize()
     for o, x in zip(outs, xs):
         np.testing.assert_array_equal(u32_host(o), x)
+
+
+@pytest.mark.parametrize("variant", [-1, 0, 2])
+def test_more_than_five_thousand_groups(variant):
+    """More than 5,000 groups (multi-tile scans of the offsets and of the sums, with sums whose top
+    bit is set); document ids and every-length values (spans past the staged part), compared in
+    full."""
+    n = 1300 * 4 * GROUP + 5
+    for name, x in (("docids", inputs.docids(n, seed=31, start=12345)[0]),
+                    ("every_length", np.cumsum(inputs.stress_lengths(n, seed=32), dtype=np.uint32))):
+        ref = oracle.encode(x, delta=True, start=17)
+        log_case("delta many groups", "variant=%d" % variant, name, "n=%d" % n)
+        got, err = decode(ref, n, 17, variant)
+        assert err == 0
+        np.testing.assert_array_equal(got, x, err_msg=name)

@@ -23,7 +23,7 @@ def _device():
     yield
     torch.cuda.synchronize()
     for delta in (False, True):
-        svb.svb_set_decode_variant(delta, 0)
+        svb.svb_set_decode_variant(delta, -1)
 
 
 def small_deltas(n, seed):
@@ -81,9 +81,9 @@ def test_autotune_decode_picks_a_variant():
     out = torch.zeros(n, dtype=torch.int32, device="cuda")
     log_case("zero-control autotune")
     v = svb.svb_autotune_decode(n, d, s.size, out, 0, True)
-    assert v in (0, 1, 2, 3)  # delta: zero-control bit, two-pass bit
+    assert v in (0, 1, 2, 3)  # delta: zero-control bit, sums-by-decoding bit
     out.zero_()
     svb.svb_delta_decode(n, d, s.size, out, 0)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(u32_host(out), x)
-    svb.svb_set_decode_variant(True, 0)
+    svb.svb_set_decode_variant(True, -1)
