@@ -16,7 +16,11 @@ Prints one JSON line.  Besides the headline it carries:
   kernels       average duration of every kernel of the call;
   cpu_baseline  the scalar C oracle, single-threaded, on the host cores;
   encode        delta encode of the same array;
-  flushed       the whole call with a 1 GiB cache-evicting write before each;
+  protocol      the headline's timing: every call after a 1 GiB read that
+                evicts the caches (the median of at least 21 calls);
+  dirty_flush   the same with a 1 GiB write before each call instead (up to
+                256 MB of its dirty lines are written back during the call);
+  unflushed     the mean of back-to-back calls;
   copy          a plain copy kernel (the practical bandwidth ceiling);
   at_2p28       delta decode of the same generator at 2^28 integers, and plain
                 decode of 2^28 integers with unpredictable lengths;
@@ -176,6 +180,98 @@ def summarize_counters(fetch_csv, write_csv, out_md, command):
     print("\n".join(lines))
 
 
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4  # 1024 SIMDs, one wave64 instruction per 4 cycles each
+
+
+def _pmc_rows(paths):
+    """Per kernel: every counter's values (one per dispatch) and the dispatch durations, over the
+    counter_collection CSVs of several rocprofv3 --pmc runs."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(list)
+    for path in paths:
+        seen = set()
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k = r["Kernel_Name"]
+                per[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                key = (k, r.get("Dispatch_Id"), path)
+                if key not in seen:
+                    seen.add(key)
+                    dur[k].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return per, dur
+
+
+def _short(name, width=70):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+    return name if len(name) <= width else name[:width - 3] + "..."
+
+
+def summarize_pmc(out_md, title, commands, paths, only=None):
+    """Every kernel of one or more rocprofv3 --pmc runs (or those whose name holds one of the
+    fragments in `only`): median dispatch duration, HBM bytes from FETCH_SIZE / WRITE_SIZE scaled
+    by what the same counters read for the copy kernel (COPY_WORDS * 4 bytes each way), and SQ
+    instruction counts per wave with the VALU issue share they imply."""
+    per, dur = _pmc_rows(paths)
+    copy = [k for k in per if COPY_SYMBOL in k]
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        if copy and per[copy[0]].get(c):
+            v = per[copy[0]][c]
+            scale[c] = 4.0 * COPY_WORDS / (1024.0 * sum(v) / len(v))
+    mean = lambda k, c: (sum(per[k][c]) / len(per[k][c])) if per[k].get(c) else None
+    med = lambda k: sorted(dur[k])[len(dur[k]) // 2] / 1e3 if dur[k] else float("nan")
+    names = [k for k in per if "svb" in k and (not only or any(f in k for f in only))]
+    names.sort(key=lambda k: -med(k))
+    lines = ["# %s" % title, "", "rocprofv3 counter runs (one per line):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Durations are the median over dispatches of the counter runs (counters serialise",
+              "dispatches, so they run somewhat longer than in a plain run)."]
+    if scale:
+        lines += ["", "HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over dispatches), each",
+                  "scaled by bytes / counter of the copy kernel of the same run (%d bytes each way):"
+                  % (4 * COPY_WORDS),
+                  " ".join("%s scale %.4f;" % (c, v) for c, v in sorted(scale.items())), "",
+                  "| kernel | dispatches | median us | fetched MB | written MB | GB/s |", "|---|---|---|---|---|---|"]
+        for k in names:
+            f, w = mean(k, "FETCH_SIZE"), mean(k, "WRITE_SIZE")
+            fb = f * 1024 * scale.get("FETCH_SIZE", 1) if f is not None else None
+            wb = w * 1024 * scale.get("WRITE_SIZE", 1) if w is not None else None
+            gb = ((fb or 0) + (wb or 0)) / (med(k) * 1e3) if (fb is not None or wb is not None) else None
+            fmt = lambda v: "%.2f" % (v / 1e6) if v is not None else "-"
+            lines.append("| `%s` | %d | %.1f | %s | %s | %s |" % (_short(k), len(dur[k]), med(k), fmt(fb), fmt(wb),
+                                                                 "%.0f" % gb if gb is not None else "-"))
+    sq = [c for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+                      "SQ_WAIT_INST_ANY") if any(per[k].get(c) for k in names)]
+    if sq and any(per[k].get("SQ_WAVES") for k in names):
+        lines += ["", "Instructions per wave (SQ counters, summed over the device, over SQ_WAVES); VALU share =",
+                  "SQ_INSTS_VALU / (%.1f G wave instructions/s x median duration): 1024 SIMDs issuing one"
+                  % (VALU_WAVE_INSTR_PER_S / 1e9),
+                  "wave64 VALU instruction per 4 cycles each at 2.4 GHz.", "",
+                  "| kernel | waves | " + " | ".join(c.replace("SQ_INSTS_", "").replace("SQ_", "").lower() + "/wave"
+                                                    for c in sq) + " | VALU share |",
+                  "|---|---|" + "---|" * len(sq) + "---|"]
+        for k in names:
+            wv = mean(k, "SQ_WAVES")
+            if not wv:
+                continue
+            cells = ["%.1f" % (mean(k, c) / wv) if mean(k, c) is not None else "-" for c in sq]
+            valu = mean(k, "SQ_INSTS_VALU")
+            share = valu / (VALU_WAVE_INSTR_PER_S * med(k) * 1e-6) if valu is not None else None
+            lines.append("| `%s` | %.0f | %s | %s |" % (_short(k), wv, " | ".join(cells),
+                                                        "%.2f" % share if share is not None else "-"))
+    other = sorted({c for k in names for c in per[k]} - set(sq) - {"SQ_WAVES", "FETCH_SIZE", "WRITE_SIZE"})
+    if other:
+        lines += ["", "Other counters (mean per dispatch):", "", "| kernel | " + " | ".join(other) + " |",
+                  "|---|" + "---|" * len(other)]
+        for k in names:
+            lines.append("| `%s` | %s |" % (_short(k), " | ".join("%.4g" % mean(k, c) if mean(k, c) is not None
+                                                                  else "-" for c in other)))
+    lines += ["", "source_digest: %s" % source_digest(), ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def summarize_trace(stats_csv, out_md, title, command, bench_json=None):
     """Turns a rocprofv3 --kernel-trace --stats kernel_stats.csv into a short table, and, given
     the bench line of the same command, puts the dominant kernel's HIP-event average beside
@@ -260,14 +356,35 @@ def timed_steps(svb, torch, fn, steps, warmup):
 MIN_REPS = 21
 
 
+class Flush:
+    """Two ways of evicting the L2s and the 256 MB MALL before a timed call, over one 1 GiB buffer:
+    clean() reads it (the caches end up holding clean lines of an unrelated buffer: the call's
+    inputs come from HBM and nothing foreign is left to write back); dirty() writes it (the caches
+    end up holding up to 256 MB of dirty lines, whose write-back then falls inside the timed call,
+    as a previous call's output would in a stream of calls)."""
+
+    def __init__(self, svb, torch):
+        self.svb = svb
+        self.buf = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+
+    def clean(self):
+        self.buf.sum()
+
+    def dirty(self):
+        self.svb.svb_fill_u32(self.buf.numel(), self.buf, 0)
+
+    def __call__(self):
+        self.clean()
+
+
 def protocol_steps(svb, torch, fn, steps, warmup, flush):
     """The measurement protocol: `warmup` untimed calls, then the timed region of exactly `steps`
-    calls between two device synchronisations, each call preceded by `flush` (a 1 GiB write that
-    evicts the L2s and the 256 MB MALL) and bracketed by events on the current stream; more
+    calls between two device synchronisations, each call preceded by flush.clean() (a 1 GiB read
+    that evicts the L2s and the 256 MB MALL) and bracketed by events on the current stream; more
     flushed calls until at least 21 have been timed.  The call time is the median of the event
     durations.  Then the same number of flushed calls with the library's per-kernel HIP events
-    (median per kernel name), and `steps` calls back to back without flushing (mean, for
-    reference).  Returns a dict."""
+    (median per kernel name), as many again after flush.dirty() (a 1 GiB write; median), and
+    `steps` calls back to back without flushing (mean, for reference).  Returns a dict."""
     for _ in range(warmup):
         flush()
         fn()
@@ -296,14 +413,22 @@ def protocol_steps(svb, torch, fn, steps, warmup, flush):
     for name, t in svb.svb_kernel_times(cap=1 << 16):
         per[name].append(t)
     kms = {k: sorted(v)[len(v) // 2] for k, v in per.items()}
+    dev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in dev:
+        flush.dirty()
+        a.record()
+        fn()
+        b.record()
     torch.cuda.synchronize()
+    dms = sorted(a.elapsed_time(b) for a, b in dev)
     t1 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
     unflushed = 1e3 * (time.perf_counter() - t1) / steps
     return {"median_ms": ms[len(ms) // 2], "reps": reps, "min_ms": ms[0], "max_ms": ms[-1],
-            "timed_region_s": wall, "kernels_ms": kms, "unflushed_mean_ms": unflushed}
+            "timed_region_s": wall, "kernels_ms": kms, "dirty_flush_median_ms": dms[len(dms) // 2],
+            "unflushed_mean_ms": unflushed}
 
 
 def gbs(nbytes, ms):
@@ -332,6 +457,10 @@ def measure_delta(svb, torch, x_dev, steps, warmup, flush):
            "ms_per_call": call_ms, "round_trip_ok": ok, "protocol": pr,
            "uint32_per_s": n / (call_ms * 1e-3), "call_GBps": gbs(alg, call_ms),
            "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS, "kernels_ms": pr["kernels_ms"],
+           "dirty_flush": {"ms_per_call": pr["dirty_flush_median_ms"],
+                           "frac_of_peak": gbs(alg, pr["dirty_flush_median_ms"]) / HBM_PEAK_GBS,
+                           "note": "median, each call after a 1 GiB write (its dirty lines are written "
+                                   "back during the call)"},
            "unflushed": {"ms_per_call": pr["unflushed_mean_ms"],
                          "frac_of_peak": gbs(alg, pr["unflushed_mean_ms"]) / HBM_PEAK_GBS,
                          "note": "mean of back-to-back calls, no cache flush"}}
@@ -343,6 +472,8 @@ def measure_delta(svb, torch, x_dev, steps, warmup, flush):
     ems = ep["median_ms"]
     res["encode"] = {"ms_per_call": ems, "uint32_per_s": n / (ems * 1e-3), "GBps": gbs(alg, ems),
                      "frac_of_peak": gbs(alg, ems) / HBM_PEAK_GBS, "kernels_ms": ep["kernels_ms"],
+                     "dirty_flush_ms": ep["dirty_flush_median_ms"],
+                     "dirty_flush_frac_of_peak": gbs(alg, ep["dirty_flush_median_ms"]) / HBM_PEAK_GBS,
                      "unflushed_ms": ep["unflushed_mean_ms"], "size_ok": int(size.item()) == nbytes}
     del comp, out
     return res
@@ -363,7 +494,9 @@ def measure_plain(svb, torch, x_dev, steps, warmup, flush):
     del comp, out
     return {"n": n, "compressed_bytes": nbytes, "ms_per_call": call_ms, "uint32_per_s": n / (call_ms * 1e-3),
             "call_GBps": gbs(alg, call_ms), "call_frac_of_peak": gbs(alg, call_ms) / HBM_PEAK_GBS,
-            "kernels_ms": pr["kernels_ms"], "unflushed_ms": pr["unflushed_mean_ms"], "round_trip_ok": ok}
+            "kernels_ms": pr["kernels_ms"], "dirty_flush_ms": pr["dirty_flush_median_ms"],
+            "dirty_flush_frac_of_peak": gbs(alg, pr["dirty_flush_median_ms"]) / HBM_PEAK_GBS,
+            "unflushed_ms": pr["unflushed_mean_ms"], "round_trip_ok": ok}
 
 
 def measure_copy(svb, torch, steps):
@@ -819,15 +952,17 @@ def run_cpu_baseline(x, min_seconds=10.0):
             "host_cpu": model, "host_threads_available": ncpu}
 
 
-ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched")
+ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched", "seek8")
 
 
-def profile_only(kind, steps, warmup, variant=None):
+def profile_only(kind, steps, warmup, variant=None, dirty=False):
     """Runs one kind of call only (`warmup` + `steps` calls, each after the 1 GiB cache-evicting
-    fill), for rocprofv3 runs that should see nothing else: delta26 / delta28 (delta decode of the
+    read, or write with `dirty`), for rocprofv3 runs that should see nothing else: delta26 / delta28 (delta decode of the
     document ids at 2^26 / 2^28), plain28 (plain decode of 2^28 integers of unpredictable length),
     encode28 (delta encode of the 2^28 document ids), batched (delta decode of the 200,000 posting
-    lists).  Prints one JSON line with the median call time by torch events."""
+    lists), seek8 (2^22 seeks over 2^20 lists of 256 running sums of deltas below 2^8).  Prints one
+    JSON line with the median call time by torch events.  One plain copy of COPY_WORDS words runs
+    after the timed calls: counter runs scale each counter by what it reads for that copy."""
     import numpy as np
     import torch
 
@@ -838,9 +973,47 @@ def profile_only(kind, steps, warmup, variant=None):
     svb.lib()
     if variant is not None:
         svb.svb_set_decode_variant(kind != "plain28", variant)
-    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-    fl = lambda: svb.svb_fill_u32(flush.numel(), flush, 0)
-    if kind == "batched":
+    flush = Flush(svb, torch)
+    fl = flush.dirty if dirty else flush.clean
+    if kind == "seek8":
+        m, q = 1 << 20, 1 << 22
+        vals, offs = inputs.seek_lists(m, 8, seed=98)
+        x_dev = torch.from_numpy(vals.view(np.int32)).cuda()
+        counts = np.full(m, 256, dtype=np.uint64)
+        u64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+        cap = svb.svb_max_compressed_bytes(256)
+        d_counts, d_val_off = u64(counts), u64(offs[:-1])
+        comp = torch.empty(m * cap, dtype=torch.uint8, device="cuda")
+        sizes = torch.empty(m, dtype=torch.int64, device="cuda")
+        starts = torch.zeros(m, dtype=torch.int32, device="cuda")
+        svb.svb_encode_batch(m, d_counts, d_val_off, x_dev, u64(np.arange(m, dtype=np.uint64) * cap), comp, sizes,
+                             starts, 256 * m)
+        torch.cuda.synchronize()
+        h_sizes = sizes.cpu().numpy().view(np.uint64).copy()
+        byte_off = np.zeros(m, dtype=np.uint64)
+        np.cumsum(h_sizes[:-1], out=byte_off[1:])
+        comp = torch.empty(int(h_sizes.sum()) + 64, dtype=torch.uint8, device="cuda")
+        d_off = u64(byte_off)
+        svb.svb_encode_batch(m, d_counts, d_val_off, x_dev, d_off, comp, sizes, starts, 256 * m)
+        index = svb.svb_seek_index_create(m, d_counts, d_off, sizes, comp, starts, 256 * m)
+        ids, targets, _ = inputs.seek_queries(vals, offs, q, seed=99)
+        d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+        d_t = torch.from_numpy(targets.view(np.int32)).cuda()
+        pos = torch.empty(q, dtype=torch.int64, device="cuda")
+        val = torch.empty(q, dtype=torch.int32, device="cuda")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        n = q
+        fn = lambda: svb.svb_seek_batch(index, q, d_ids, d_t, pos, val, err)
+
+        def check():
+            ok = int(err.item()) == 0
+            ph, vh = pos.cpu().numpy(), val.cpu().numpy().view(np.uint32)
+            for k in range(0, q, q // 1000):
+                x = vals[offs[ids[k]]:offs[ids[k] + 1]]
+                p = int(np.searchsorted(x, targets[k], side="left"))
+                ok &= (int(ph[k]), int(vh[k])) == (p, int(x[p]) if p < x.size else 0)
+            return ok
+    elif kind == "batched":
         vals, offs = inputs.posting_lists()
         m = offs.size - 1
         counts = np.diff(offs).astype(np.uint64)
@@ -897,6 +1070,14 @@ def profile_only(kind, steps, warmup, variant=None):
     ms = sorted(a.elapsed_time(b) for a, b in ev)
     med = ms[len(ms) // 2]
     ok = check()
+    if kind == "seek8":
+        svb.svb_seek_index_destroy(index)
+    del x_dev, comp, flush
+    ca = torch.empty(COPY_WORDS, dtype=torch.int32, device="cuda").fill_(7)
+    cb = torch.empty_like(ca)
+    svb.svb_copy_u32(COPY_WORDS, ca, cb)
+    torch.cuda.synchronize()
+    ok &= bool(torch.equal(ca, cb))
     print(json.dumps({"only": kind, "variant": variant, "n": n, "steps": steps, "warmup": warmup, "median_ms": med,
                       "uint32_per_s": n / (med * 1e-3), "ok": ok}))
     if not ok:
@@ -909,6 +1090,8 @@ def main():
                     help="run one kind of call only (for profiler runs) and print its median time")
     ap.add_argument("--decode-variant", type=int, default=None,
                     help="with --only: the decoder variant to set first (svb_set_decode_variant)")
+    ap.add_argument("--dirty-flush", action="store_true",
+                    help="with --only: evict the caches by writing the 1 GiB buffer instead of reading it")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
@@ -928,6 +1111,12 @@ def main():
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
                     "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
                     "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control --no-compare")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="OUT_MD TITLE CSV [CSV ...]: summary of rocprofv3 --pmc runs (every kernel); the "
+                         "commands that made them go in --pmc-command, once each")
+    ap.add_argument("--pmc-command", action="append", default=[])
+    ap.add_argument("--pmc-only", action="append", default=None,
+                    help="with --summarize-pmc: only kernels whose name holds this fragment (repeatable)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
                     "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
@@ -938,6 +1127,12 @@ def main():
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, command=args.trace_command, bench_json=args.trace_bench_json)
         return
+    if args.summarize_pmc:
+        if len(args.summarize_pmc) < 3:
+            ap.error("--summarize-pmc needs OUT_MD TITLE CSV [CSV ...]")
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command, args.summarize_pmc[2:],
+                      args.pmc_only)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, command=args.counter_command)
         return
@@ -946,7 +1141,7 @@ def main():
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.only:
-        profile_only(args.only, args.steps, args.warmup, args.decode_variant)
+        profile_only(args.only, args.steps, args.warmup, args.decode_variant, args.dirty_flush)
         return
 
     import numpy as np
@@ -960,8 +1155,7 @@ def main():
     log("generating %d document ids" % N_HEAD)
     x, _ = inputs.docids(N_HEAD, seed=2)
     x_dev = torch.from_numpy(x.view(np.int32)).cuda()
-    flush_buf = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
-    flush = lambda: svb.svb_fill_u32(flush_buf.numel(), flush_buf, 0)
+    flush = Flush(svb, torch)
     log("delta decode: %d warmup + %d timed steps (at least %d flushed reps)" % (args.warmup, args.steps, MIN_REPS))
     r = measure_delta(svb, torch, x_dev, args.steps, args.warmup, flush)
     assert r["round_trip_ok"], "delta decode did not reproduce the input"
@@ -987,7 +1181,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N_HEAD, "compressed_bytes": r["compressed_bytes"],
                    "bits_per_int": round(r["bits_per_int"], 4), "parallelism": "none (1 GPU)",
-                   "timing": "median of %d calls, each after a 1 GiB cache-evicting fill (HIP events)"
+                   "timing": "median of %d calls, each after a 1 GiB cache-evicting read (HIP events)"
                              % r["protocol"]["reps"]},
         # the dominant kernel reads the control and data bytes and writes every integer: its
         # algorithmic bytes are the call's
@@ -999,6 +1193,7 @@ def main():
                                     "frac": r["call_frac_of_peak"]}},
         "kernels_ms": r["kernels_ms"],
         "protocol": r["protocol"],
+        "dirty_flush": r["dirty_flush"],
         "unflushed": r["unflushed"],
         "encode": r["encode"],
         "copy": copy,
@@ -1017,7 +1212,7 @@ def main():
             % (r2["ms_per_call"], 100 * r2["call_frac_of_peak"]))
         line["at_2p28"] = {"delta_docids": {k: r2[k] for k in (
             "n", "compressed_bytes", "ms_per_call", "uint32_per_s", "call_GBps", "call_frac_of_peak", "kernels_ms",
-            "unflushed", "encode")}}
+            "dirty_flush", "unflushed", "encode")}}
         log("2^28 delta encode %.4f ms/call (%.1f%% of peak)"
             % (r2["encode"]["ms_per_call"], 100 * r2["encode"]["frac_of_peak"]))
         log("generating %d stress integers" % n2)
@@ -1029,7 +1224,7 @@ def main():
         del x3_dev
         log("2^28 plain decode %.4f ms/call (%.1f%% of peak)" % (r3["ms_per_call"], 100 * r3["call_frac_of_peak"]))
         line["at_2p28"]["plain_stress"] = r3
-    del flush_buf
+    del flush
     if not args.no_batched:
         log("batched: generating 200,000 posting lists")
         rb = measure_batched(svb, torch, np, inputs, max(5, args.steps // 2), 2, per_list=not args.no_per_list)

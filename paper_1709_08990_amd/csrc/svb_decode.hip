@@ -103,13 +103,22 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 //   kSums:  store nothing; write the group's sum of decoded values to gvsum.
 //   ZC: rows of all-zero control bytes take the widening path of
 //       extract_segment (the zero-control variant).
+// Delta decoding takes the groups last to first: the value-sum pass has just
+// read the stream front to back, so the end of it is still in the
+// memory-side cache when the decode starts (measured at 2^28 document ids:
+// 0.385 ms per call against 0.400 front to back; no change at 2^26, whose
+// whole stream stays cached either way).
+#ifndef SVB_DECODE_REVERSE
+#define SVB_DECODE_REVERSE 1
+#endif
 template <int MODE, bool ZC>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const uint32_t *goff32) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-    const uint64_t g = (uint64_t)blockIdx.x * kWaves + wave;
-    if (g >= p.groups) return;
+    const uint64_t gl = (uint64_t)blockIdx.x * kWaves + wave;
+    if (gl >= p.groups) return;
+    const uint64_t g = (MODE == kDelta && SVB_DECODE_REVERSE) ? p.groups - 1 - gl : gl;
     uint8_t *stage = s_stage + wave * kStageBytes;
     const uint64_t segs = (p.n + kSegInts - 1) / kSegInts;
     const uint64_t s0 = g * kGroupSegs;

@@ -39,6 +39,13 @@ __global__ __launch_bounds__(kThreads) void encode_sizes_kernel(EncodeStream e, 
     if (lane == 0) seg_bytes[s] = t;
 }
 
+// The pack pass takes the segments last to first: the size pass has just read
+// the values front to back, so the end of them is still in the memory-side
+// cache (measured at 2^28 document ids: 0.441 ms per delta encode against
+// 0.446 front to back).
+#ifndef SVB_PACK_REVERSE
+#define SVB_PACK_REVERSE 1
+#endif
 template <bool DELTA>
 __global__ __launch_bounds__(kThreads) void encode_pack_kernel(EncodeStream e, const uint64_t *seg_off,
                                                                const uint32_t *seg_off32, uint64_t segs,
@@ -46,8 +53,9 @@ __global__ __launch_bounds__(kThreads) void encode_pack_kernel(EncodeStream e, c
     __shared__ __attribute__((aligned(16))) uint32_t s_stage[kWaves * (kEncStageBytes / 4)];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t s = (uint64_t)blockIdx.x * kWaves + wave;
-    if (s >= segs) return;
+    const uint64_t sl = (uint64_t)blockIdx.x * kWaves + wave;
+    if (sl >= segs) return;
+    const uint64_t s = SVB_PACK_REVERSE ? segs - 1 - sl : sl;
     const uint64_t off = seg_off32 ? (uint64_t)seg_off32[s] : seg_off[s];
     const uint32_t t = encode_segment<DELTA>(e, s, off, lane, s_stage + wave * (kEncStageBytes / 4));
     if (s == segs - 1 && lane == 0 && out_bytes) *out_bytes = (e.n + 3) / 4 + off + t;
