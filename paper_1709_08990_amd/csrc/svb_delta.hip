@@ -46,7 +46,8 @@ namespace {
 static_assert(kGroupCtrl == 16 * kWave, "the value-sum step gives each lane 16 control bytes of a group");
 
 constexpr uint32_t kSpanStage = 4608;  // 288 chunks: a document-id group's span fits
-constexpr uint32_t kSumLds = kSpanStage;
+constexpr uint32_t kCorrList = 64;     // blocks with a non-zero control byte listed for one pass
+constexpr uint32_t kSumLds = kSpanStage + 4 * kCorrList;
 
 __device__ __forceinline__ uint32_t sad_bytes(uint32_t x, uint32_t acc) { return __builtin_amdgcn_sad_u8(x, 0u, acc); }
 
@@ -206,28 +207,18 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // corrections: each of the lane's blocks with a non-zero control byte,
-    // read from the staged span (an integer's 4-byte read starts at most 12
-    // bytes into its block and reads 8 aligned bytes, so a block whose first
-    // byte lies 24 bytes or more before the staged part's end reads only
-    // staged bytes; bytes past the span never reach a value, masked to the
-    // integer's length), or else from its two aligned chunks in memory
+    // corrections: each block with a non-zero control byte, read from the
+    // staged span (an integer's 4-byte read starts at most 12 bytes into its
+    // block and reads 8 aligned bytes, so a block whose first byte lies 24
+    // bytes or more before the staged part's end reads only staged bytes;
+    // bytes past the span never reach a value, masked to the integer's
+    // length), or else from its two aligned chunks in memory
     const uint64_t b0 = sl.g * kGroupCtrl + 16ull * lane;
     const uint64_t last_block = nblocks - 1;
     const uint32_t last_r = (uint32_t)(((p.n - 1) & 3) + 1);
-    uint32_t corr = 0;
-    uint32_t m = nzm;
-    while (m) {
-        const uint32_t b = __builtin_ctz(m);
-        m &= m - 1u;
-        const uint32_t i = b >> 2, k = b & 3u;
-        const uint32_t ci = pick4(i, sl.c[0], sl.c[1], sl.c[2], sl.c[3]);
-        const uint32_t low = ci & low_bytes_mask((int32_t)k);
-        const uint32_t boff = off + 4 * b + pick4(i, pre[0], pre[1], pre[2], pre[3]) + __builtin_popcount(low) +
-                              __builtin_popcount(low & 0xAAAAAAAAu);
-        const uint32_t cb = (ci >> (8 * k)) & 0xFFu;
-        const uint32_t r = (b0 + b == last_block) ? last_r : 4u;
-        const uint32_t pos = sh16 + boff;  // the block's first byte, from abase
+    // the correction of one block: its first byte at pos (from abase), control byte cb, r integers
+    auto block_corr = [&](uint32_t pos, uint32_t cb, uint32_t r) -> uint32_t {
+        uint32_t corr = 0;
         if (pos + 24 <= staged) {
             uint32_t q = pos;
 #pragma unroll
@@ -255,6 +246,51 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
                 corr += v - sad_bytes(v, 0u);
                 q += L;
             }
+        }
+        return corr;
+    };
+    // where block b of the lane (0..15) starts, its control byte and integer count
+    auto block_at = [&](uint32_t b, uint32_t &pos, uint32_t &cb, uint32_t &r) {
+        const uint32_t i = b >> 2, k = b & 3u;
+        const uint32_t ci = pick4(i, sl.c[0], sl.c[1], sl.c[2], sl.c[3]);
+        const uint32_t low = ci & low_bytes_mask((int32_t)k);
+        pos = sh16 + off + 4 * b + pick4(i, pre[0], pre[1], pre[2], pre[3]) + __builtin_popcount(low) +
+              __builtin_popcount(low & 0xAAAAAAAAu);
+        cb = (ci >> (8 * k)) & 0xFFu;
+        r = (b0 + b == last_block) ? last_r : 4u;
+    };
+    // the blocks with a non-zero control byte are few on most streams but
+    // unevenly spread over the lanes: up to kCorrList of them are listed in
+    // LDS and taken one per lane; more are taken by their own lanes
+    const uint32_t nzc = __builtin_popcount(nzm);
+    const uint32_t nzi = wave_incl_scan(nzc);
+    const uint32_t nz_total = wave_last(nzi);
+    uint32_t corr = 0;
+    uint32_t m = nzm;
+    if (nz_total <= kCorrList) {
+        uint32_t *list = (uint32_t *)(stage + kSpanStage);
+        uint32_t slot = nzi - nzc;
+        while (m) {
+            const uint32_t b = __builtin_ctz(m);
+            m &= m - 1u;
+            uint32_t pos, cb, r;
+            block_at(b, pos, cb, r);
+            list[slot++] = pos | (cb << 20) | ((r - 1u) << 28);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nz_total) {
+            const uint32_t e = list[lane];
+            corr = block_corr(e & 0xFFFFFu, (e >> 20) & 0xFFu, (e >> 28) + 1u);
+        }
+    } else {
+        while (m) {
+            const uint32_t b = __builtin_ctz(m);
+            m &= m - 1u;
+            uint32_t pos, cb, r;
+            block_at(b, pos, cb, r);
+            corr += block_corr(pos, cb, r);
         }
     }
     // the next use of the area overwrites it: LDS operations of a wave complete in order

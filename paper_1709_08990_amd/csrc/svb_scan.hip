@@ -13,10 +13,12 @@
 //
 // Up to kSingleMax (16384) values: one workgroup of 1024 threads.  Above
 // that: reduce-then-scan over tiles of 4096 values, one 256-thread workgroup
-// each (tile sums, one-workgroup scan of the tile sums, per-tile scan with
-// carry), so that a few hundred thousand values already spread over most of
-// the chip; one workgroup walking a longer array step by step was measured
-// slower than the three launches.
+// each, in two launches (tile sums; then each tile adds up the sums of the
+// tiles before it and scans its values from there), so that a few hundred
+// thousand values already spread over most of the chip.  Measured at 65,536
+// values: one workgroup taking them in one step of 64 per thread, 18.5 us;
+// three launches (with a one-workgroup scan of the tile sums between), about
+// 10 us; the two launches save the middle one.
 #include <type_traits>
 
 #include "svb_device.hpp"
@@ -186,35 +188,28 @@ __global__ __launch_bounds__(kTileThreads) void scan_tile_sums_kernel(const uint
     }
 }
 
-// Exclusive scan of the tile sums by one workgroup (at most a few thousand).
-template <bool WIDE>
-__global__ __launch_bounds__(kScanThreads) void scan_tile_prefix_kernel(const uint32_t *sums, uint64_t tiles,
-                                                                        uint64_t *pre, uint32_t start, void *total) {
-    typedef acc_t<WIDE> A;
-    constexpr uint32_t W = kScanThreads / kWave;
-    __shared__ A s_wtot[W + 1];
-    const uint32_t tid = threadIdx.x;
-    A carry = WIDE ? (A)0 : (A)start;
-    for (uint64_t base = 0; base < tiles; base += kScanThreads) {
-        const uint64_t t = base + tid;
-        A v = 0;
-        if (t < tiles) v = WIDE ? (A)(sums[2 * t] | ((uint64_t)sums[2 * t + 1] << 32)) : (A)sums[t];
-        A step_total;
-        const A p = block_prefix<W, A>(v, s_wtot, &step_total);
-        if (t < tiles) pre[t] = (uint64_t)(carry + p);
-        carry += step_total;
-    }
-    if (tid == 0) write_total<WIDE>(total, carry);
-}
+// Per-tile scan that takes its own carry, the sum of the tile sums before it
+// (`start` on top, when not WIDE), so that no separate scan of the tile sums
+// runs between the two passes.  Tile t reads t sums: a few per thread up to
+// millions of values (2^22 values, 1024 tiles: at most 4 per thread).  The
+// last tile writes the total.
 
-// Per-tile scan with the tile's carry.
 template <bool WIDE>
-__global__ __launch_bounds__(kTileThreads) void scan_tile_final_kernel(const uint32_t *in, void *out, uint64_t m,
-                                                                       const uint64_t *pre) {
+__global__ __launch_bounds__(kTileThreads) void scan_tile_carry_final_kernel(const uint32_t *in, void *out, uint64_t m,
+                                                                             const uint32_t *sums, uint32_t start,
+                                                                             void *total) {
     typedef acc_t<WIDE> A;
     constexpr uint32_t W = kTileThreads / kWave;
+    __shared__ A s_acc[W + 1];
     __shared__ uint32_t s_wtot[W + 1];
-    const uint64_t base = (uint64_t)blockIdx.x * kTileVals;
+    const uint64_t tile = blockIdx.x;
+    A c = 0;
+    for (uint64_t t = threadIdx.x; t < tile; t += kTileThreads)
+        c += WIDE ? (A)(sums[2 * t] | ((uint64_t)sums[2 * t + 1] << 32)) : (A)sums[t];
+    A before;
+    (void)block_prefix<W, A>(c, s_acc, &before);
+    const A carry = (WIDE ? (A)0 : (A)start) + before;
+    const uint64_t base = tile * kTileVals;
     uint32_t x[kScanPer];
     load16(in, base, m, threadIdx.x, x);
     uint32_t sum = 0;
@@ -222,7 +217,8 @@ __global__ __launch_bounds__(kTileThreads) void scan_tile_final_kernel(const uin
     for (uint32_t j = 0; j < kScanPer; ++j) sum += x[j];
     uint32_t tot;
     const uint32_t p = block_prefix<W, uint32_t>(sum, s_wtot, &tot);
-    store16<WIDE>(out, base, m, threadIdx.x, (A)pre[blockIdx.x], p, x);
+    store16<WIDE>(out, base, m, threadIdx.x, carry, p, x);
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) write_total<WIDE>(total, carry + (A)tot);
 }
 
 }  // namespace
@@ -230,7 +226,7 @@ __global__ __launch_bounds__(kTileThreads) void scan_tile_final_kernel(const uin
 uint64_t scan_scratch_bytes(uint64_t m) {
     if (m <= kSingleMax) return 0;
     const uint64_t tiles = (m + kTileVals - 1) / kTileVals;
-    return 8 * tiles + 8 * tiles;  // tile sums (two words each when wide), tile prefixes
+    return 8 * tiles;  // tile sums (two words each when wide)
 }
 
 hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
@@ -245,19 +241,14 @@ hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uin
     if (!scratch) return hipErrorInvalidValue;
     const uint64_t tiles = (m + kTileVals - 1) / kTileVals;
     uint32_t *sums = (uint32_t *)scratch;
-    uint64_t *pre = (uint64_t *)((uint8_t *)scratch + 8 * tiles);
     if (wide) {
         hipLaunchKernelGGL((scan_tile_sums_kernel<true>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, m, sums);
-        hipLaunchKernelGGL((scan_tile_prefix_kernel<true>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
-                           total);
-        hipLaunchKernelGGL((scan_tile_final_kernel<true>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, out, m,
-                           pre);
+        hipLaunchKernelGGL((scan_tile_carry_final_kernel<true>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in,
+                           out, m, sums, start, total);
     } else {
         hipLaunchKernelGGL((scan_tile_sums_kernel<false>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, m, sums);
-        hipLaunchKernelGGL((scan_tile_prefix_kernel<false>), dim3(1), dim3(kScanThreads), 0, s, sums, tiles, pre, start,
-                           total);
-        hipLaunchKernelGGL((scan_tile_final_kernel<false>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in, out, m,
-                           pre);
+        hipLaunchKernelGGL((scan_tile_carry_final_kernel<false>), dim3((uint32_t)tiles), dim3(kTileThreads), 0, s, in,
+                           out, m, sums, start, total);
     }
     return hipGetLastError();
 }
