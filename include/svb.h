@@ -131,6 +131,24 @@ int svb_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, 
 int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out,
                      uint32_t start, uint32_t *err, void *stream);
 
+/* svb_delta_decode_noalloc -- svb_delta_decode for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, output, error behaviour
+ * and kernels as svb_delta_decode, but its scratch is a fixed 8 MiB array in
+ * the library's device code instead of the per-stream workspace: it never
+ * calls hipMalloc, hipFree or any allocating routine.  Each device the
+ * library runs on holds its own copy of the array until the process ends;
+ * the first call on a device looks up that device's address of it.  n is
+ * limited to SVB_NOALLOC_MAX_N (2^30): larger n is SVB_ERR_INVALID.  Every
+ * call on one device shares that device's array, whose contents carry no
+ * meaning from one call to the next (nothing in it needs to start at any
+ * value): calls that overlap on one device -- on different streams, or from
+ * different threads without ordering -- race on it and give wrong results.
+ * Per-kernel timing (svb_set_kernel_timing) does not apply to it. */
+#define SVB_NOALLOC_MAX_N (((uint64_t)1) << 30)
+int svb_delta_decode_noalloc(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out,
+                             uint32_t start, uint32_t *err, void *stream);
+
 /*
  * Batched calls (Section 5's posting lists: many lists of very uneven
  * length): m independent lists decoded or encoded by one fixed sequence of

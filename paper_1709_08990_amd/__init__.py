@@ -13,7 +13,8 @@ import os
 
 __all__ = [
     "SvbError", "lib", "svb_control_bytes", "svb_max_compressed_bytes", "svb_encode",
-    "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_encode_batch", "svb_decode_batch",
+    "svb_delta_encode", "svb_decode", "svb_delta_decode", "svb_delta_decode_noalloc", "svb_encode_batch",
+    "svb_decode_batch",
     "svb_strerror", "svb_release_workspace", "svb_version", "svb_copy_u32", "svb_fill_u32",
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
@@ -58,6 +59,7 @@ def lib():
             "svb_delta_encode": (i32, [u64, vp, vp, u32, vp, vp]),
             "svb_decode": (i32, [u64, vp, u64, vp, vp, vp]),
             "svb_delta_decode": (i32, [u64, vp, u64, vp, u32, vp, vp]),
+            "svb_delta_decode_noalloc": (i32, [u64, vp, u64, vp, u32, vp, vp]),
             "svb_encode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp]),
             "svb_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp]),
             "svb_autotune_decode_batch": (i32, [u32, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp, vp]),
@@ -170,6 +172,15 @@ def svb_delta_decode(n, inp, in_bytes, out, start=0, err=None, stream=None):
     return _check(lib().svb_delta_decode(int(n), _ptr(inp), int(in_bytes), _ptr(out),
                                          int(start) & 0xFFFFFFFF, _ptr(err), _stream(stream)),
                   "svb_delta_decode")
+
+
+SVB_NOALLOC_MAX_N = 1 << 30
+
+
+def svb_delta_decode_noalloc(n, inp, in_bytes, out, start=0, err=None, stream=None):
+    return _check(lib().svb_delta_decode_noalloc(int(n), _ptr(inp), int(in_bytes), _ptr(out),
+                                                 int(start) & 0xFFFFFFFF, _ptr(err), _stream(stream)),
+                  "svb_delta_decode_noalloc")
 
 
 def _total_ints(total_ints):

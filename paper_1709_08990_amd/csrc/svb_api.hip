@@ -147,55 +147,58 @@ int variant_choice(bool delta) {
     return it == g_variant.end() ? -1 : it->second;
 }
 
-// variant: -1 = the chosen variant for this kind of call, else the bits above.
-int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
-              uint32_t *err, bool delta, void *stream, int variant = -1) {
-    hipStream_t s = (hipStream_t)stream;
-    if (n > SVB_MAX_N) return SVB_ERR_INVALID;
-    if (err && !aligned4(err)) return SVB_ERR_INVALID;
-    if (n == 0) return SVB_OK;
-    if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
-    if (in_bytes < (n + 3) / 4) return SVB_ERR_INVALID;
-    const uint64_t groups = (n + kGroupInts - 1) / kGroupInts;
-    // scratch: per group data bytes (u32), data offset (u64), value sum (u32),
-    // value prefix (u32)
+// Scratch layout of a decode of n integers: per group data bytes (u32), data
+// offset (u64, or u32 when the stream is under 4 GiB), value sum (u32), value
+// prefix (u32), then the scans' partial sums.
+struct DecodeLayout {
+    uint64_t groups, o_gbytes, o_goff, o_gvsum, o_gvpre, o_scan, need;
+};
+
+DecodeLayout decode_layout(uint64_t n) {
     auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
-    const uint64_t o_gbytes = 0;
-    const uint64_t o_goff = o_gbytes + up16(4 * groups);
-    const uint64_t o_gvsum = o_goff + up16(8 * (groups + 1));
-    const uint64_t o_gvpre = o_gvsum + up16(4 * groups);
-    const uint64_t o_scan = o_gvpre + up16(4 * groups);
-    const uint64_t need = o_scan + up16(scan_scratch_bytes(groups));
-    std::lock_guard<std::mutex> lock(g_mu);
-    const int chosen = variant < 0 ? variant_choice(delta) : variant;
+    DecodeLayout L;
+    L.groups = (n + kGroupInts - 1) / kGroupInts;
+    L.o_gbytes = 0;
+    L.o_goff = L.o_gbytes + up16(4 * L.groups);
+    L.o_gvsum = L.o_goff + up16(8 * (L.groups + 1));
+    L.o_gvpre = L.o_gvsum + up16(4 * L.groups);
+    L.o_scan = L.o_gvpre + up16(4 * L.groups);
+    L.need = L.o_scan + up16(scan_scratch_bytes(L.groups));
+    return L;
+}
+
+// The decoder's launches on stream s over scratch sc (L.need bytes; nothing
+// in it needs to start at any value).  Arguments are checked by the caller,
+// n > 0; g_mu held.  With `timing`, launches may be bracketed by the
+// per-kernel timing events.
+int decode_launches(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start, uint32_t *err,
+                    bool delta, hipStream_t s, int chosen, uint8_t *sc, const DecodeLayout &L, bool timing) {
+    auto run = [&](const char *name, auto launch) { return hip_status(timing ? timed(name, s, launch) : launch()); };
+    const uint64_t groups = L.groups;
     const bool zc = chosen > 0 && (chosen & kVariantZC) != 0;
     const bool sums_by_decoding = chosen < 0 ? (in_bytes - (n + 3) / 4) / groups > kByteSumsMaxSpan
                                              : (chosen & kVariantSumsByDecoding) != 0;
-    Workspace *w;
-    int st = acquire_locked(s, &w);
-    if (st != SVB_OK) return st;
-    if ((st = ensure_scratch(*w, need, s)) != SVB_OK) return st;
-    uint8_t *sc = w->scratch;
-
+    int st;
     // data-stream offset of every group (and segment), from the control stream
     GroupBytesArgs ga;
     ga.in = in;
     ga.in_bytes = in_bytes;
     ga.n = n;
     ga.groups = groups;
-    ga.gbytes = (uint32_t *)(sc + o_gbytes);
-    if ((st = hip_status(timed("group_bytes", s, [&] { return launch_group_bytes(ga, s); }))) != SVB_OK) return st;
+    ga.gbytes = (uint32_t *)(sc + L.o_gbytes);
+    if ((st = run("group_bytes", [&] { return launch_group_bytes(ga, s); })) != SVB_OK) return st;
     // offsets below 2^32 (a data stream under 4 GiB) scan in 32 bits: half
     // the bytes written and read
     const bool off32 = in_bytes < (1ull << 32);
     // the total lands after the last group's offset (the value-sum pass reads
     // each group's end)
-    void *goff_end = off32 ? (void *)((uint32_t *)(sc + o_goff) + groups) : (void *)((uint64_t *)(sc + o_goff) + groups);
-    if ((st = hip_status(timed("scan_offsets", s, [&] {
-             return launch_scan(ga.gbytes, sc + o_goff, groups, !off32, 0u, s, goff_end, sc + o_scan);
-         }))) != SVB_OK)
+    void *goff_end = off32 ? (void *)((uint32_t *)(sc + L.o_goff) + groups)
+                           : (void *)((uint64_t *)(sc + L.o_goff) + groups);
+    if ((st = run("scan_offsets", [&] {
+             return launch_scan(ga.gbytes, sc + L.o_goff, groups, !off32, 0u, s, goff_end, sc + L.o_scan);
+         })) != SVB_OK)
         return st;
-    const uint32_t *goff32 = off32 ? (const uint32_t *)(sc + o_goff) : nullptr;
+    const uint32_t *goff32 = off32 ? (const uint32_t *)(sc + L.o_goff) : nullptr;
 
     DecodeArgs a = {};
     a.in = in;
@@ -204,23 +207,71 @@ int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, u
     a.out = out;
     a.err = err;
     a.groups = groups;
-    a.goff = (const uint64_t *)(sc + o_goff);
-    a.gvsum = (uint32_t *)(sc + o_gvsum);
-    a.gvpre = (const uint32_t *)(sc + o_gvpre);
+    a.goff = (const uint64_t *)(sc + L.o_goff);
+    a.gvsum = (uint32_t *)(sc + L.o_gvsum);
+    a.gvpre = (const uint32_t *)(sc + L.o_gvpre);
     if (delta) {
         // value sum of every group, then start + their exclusive prefix
-        if ((st = hip_status(timed("group_sums", s, [&] {
+        if ((st = run("group_sums", [&] {
                  return sums_by_decoding ? launch_decode(a, kSums, s, zc, goff32) : launch_group_sums(a, goff32, s);
-             }))) != SVB_OK)
+             })) != SVB_OK)
             return st;
-        if ((st = hip_status(timed("scan_sums", s, [&] {
-                 return launch_scan(a.gvsum, sc + o_gvpre, groups, false, start, s, nullptr, sc + o_scan);
-             }))) != SVB_OK)
+        if ((st = run("scan_sums", [&] {
+                 return launch_scan(a.gvsum, sc + L.o_gvpre, groups, false, start, s, nullptr, sc + L.o_scan);
+             })) != SVB_OK)
             return st;
     }
-    return hip_status(
-        timed(delta ? "decode_delta" : "decode", s,
-              [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc, goff32); }));
+    return run(delta ? "decode_delta" : "decode", [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc, goff32); });
+}
+
+// Argument checks shared by the decode entry points: SVB_OK to go on, 1 for
+// nothing to do (n = 0), else an error.
+int check_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, const uint32_t *out, const uint32_t *err) {
+    if (n > SVB_MAX_N) return SVB_ERR_INVALID;
+    if (err && !aligned4(err)) return SVB_ERR_INVALID;
+    if (n == 0) return 1;
+    if (!in || !out || !aligned4(out)) return SVB_ERR_INVALID;
+    if (in_bytes < (n + 3) / 4) return SVB_ERR_INVALID;
+    return SVB_OK;
+}
+
+// variant: -1 = the chosen variant for this kind of call, else the bits above.
+int do_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
+              uint32_t *err, bool delta, void *stream, int variant = -1) {
+    hipStream_t s = (hipStream_t)stream;
+    int st = check_decode(n, in, in_bytes, out, err);
+    if (st != SVB_OK) return st == 1 ? SVB_OK : st;
+    const DecodeLayout L = decode_layout(n);
+    std::lock_guard<std::mutex> lock(g_mu);
+    const int chosen = variant < 0 ? variant_choice(delta) : variant;
+    Workspace *w;
+    if ((st = acquire_locked(s, &w)) != SVB_OK) return st;
+    if ((st = ensure_scratch(*w, L.need, s)) != SVB_OK) return st;
+    return decode_launches(n, in, in_bytes, out, start, err, delta, s, chosen, w->scratch, L, true);
+}
+
+// Scratch of svb_delta_decode_noalloc: one file-scope array per device (each
+// device holds its own copy for the life of the process).  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): the address each device gives for it is looked up once,
+// with that device current, and kept in g_static_scratch.
+constexpr uint64_t kStaticScratchBytes = 8ull << 20;  // n up to SVB_NOALLOC_MAX_N = 2^30 needs about 5 MiB
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+uint8_t *g_static_scratch[kMaxDevices] = {};
+
+// The calling thread's device's address of `scratch`.  Caller holds g_mu.
+int static_scratch_locked(uint8_t **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return SVB_ERR_INVALID;
+    if (!g_static_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SVB_ERR_HIP;
+        g_static_scratch[dev] = (uint8_t *)ptr;
+    }
+    *out = g_static_scratch[dev];
+    return SVB_OK;
 }
 
 // Times the decoder variants (plain: general and zero-control; delta: those
@@ -732,6 +783,21 @@ int svb_delta_decode(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t 
                      uint32_t *err, void *stream) {
     return do_decode(n, in, in_bytes, out, start, err, true, stream);
 }
+
+int svb_delta_decode_noalloc(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *out, uint32_t start,
+                             uint32_t *err, void *stream) {
+    int st = check_decode(n, in, in_bytes, out, err);
+    if (st != SVB_OK) return st == 1 ? SVB_OK : st;
+    if (n > SVB_NOALLOC_MAX_N) return SVB_ERR_INVALID;
+    const DecodeLayout L = decode_layout(n);
+    if (L.need > kStaticScratchBytes) return SVB_ERR_INVALID;  // not reached for n <= SVB_NOALLOC_MAX_N
+    std::lock_guard<std::mutex> lock(g_mu);
+    uint8_t *sc = nullptr;
+    if ((st = static_scratch_locked(&sc)) != SVB_OK) return st;
+    return decode_launches(n, in, in_bytes, out, start, err, true, (hipStream_t)stream, variant_choice(true), sc, L,
+                           false);
+}
+
 
 int svb_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint32_t *in,
                      const uint64_t *out_off, uint8_t *out, uint64_t *out_bytes, const uint32_t *starts,
