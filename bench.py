@@ -39,8 +39,10 @@ Prints one JSON line.  Besides the headline it carries:
                 the general decoder and with the zero-control variant;
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
-                then Poisson arrivals at 0.5x and 0.8x of it, p50/p99 latency
-                and integers/s.
+                then Poisson arrivals at 0.5x and 0.8x of it (windows of
+                --serve-seconds, 30 s by default), p50/p99 latency and
+                integers/s, against the 2^28 single-array rate and against
+                the pool's integers decoded as one array.
 
 `python bench.py --summarize-counters FETCH.csv WRITE.csv OUT.md` turns two
 rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE) into the
@@ -825,7 +827,7 @@ def latency_summary(lat, ints, wall):
 
 
 def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
-                    arena_bytes=1 << 30, slots=4, max_batch_lists=8192):
+                    arena_bytes=1 << 30, slots=16, max_batch_lists=16384):
     """Serving loop over a device-resident pool of delta-coded posting lists: closed-loop saturation,
     then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate, then the highest probed
     Poisson rate an open loop sustains and 0.5x / 0.8x of that; each query 2..8 lists chosen
@@ -855,8 +857,23 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
             ok = ok and torch.equal(got[:n], want)
             server.release(qid)
             seen += 1
-    del pool["vals"]
     assert ok, "served results differ from the pool's source values"
+    # the same integers as one delta-coded array: the single-array rate for data of this density
+    n_all = pool["vals"].numel()
+    comp = torch.empty(svb.svb_max_compressed_bytes(n_all), dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.int64, device="cuda")
+    svb.svb_delta_encode(n_all, pool["vals"], comp, 0, size)
+    torch.cuda.synchronize()
+    nb = int(size.item())
+    out = torch.empty(n_all, dtype=torch.int32, device="cuda")
+    flush = Flush(svb, torch)
+    pr = protocol_steps(svb, torch, lambda: svb.svb_delta_decode(n_all, comp, nb, out, 0), MIN_REPS, 2, flush)
+    same_ok = bool(torch.equal(out, pool["vals"]))
+    same = {"n": n_all, "compressed_bytes": nb, "ms_per_call": pr["median_ms"],
+            "uint32_per_s": n_all / (pr["median_ms"] * 1e-3), "round_trip_ok": same_ok}
+    del comp, out, flush, pool["vals"]
+    assert same_ok, "the pool's integers as one array did not round-trip"
+    log("serving: the pool's %d integers as one array decode at %.3g ints/s" % (n_all, same["uint32_per_s"]))
 
     def query_ints(qoff, ids):
         c = h_counts[ids]
@@ -892,34 +909,6 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
         opened.append(r)
         log("serving open loop %.1fx: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
             % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
-    # what an open loop sustains: the highest probed Poisson rate that keeps up (p50 under 1 ms)
-    sustained = 0.0
-    for frac in (0.2, 0.3, 0.4, 0.5, 0.6):
-        rate = frac * sat["qps"]
-        times, qo, ids = inputs.poisson_queries_flat(int(rate * (1.0 + warmup)), rate, lists, seed=131 + int(100 * frac))
-        lat, wall = server.replay((qo, ids), arrivals=times)
-        keep = times >= warmup
-        ok = np.percentile(lat[keep], 50) < 1e-3 and lat.size / wall > 0.95 * rate
-        log("serving open-loop probe %.2fx: %s" % (frac, "keeps up" if ok else "falls behind"))
-        if not ok:
-            break
-        sustained = rate
-    at_sustained = []
-    for load in (0.5, 0.8):
-        rate = load * sustained
-        if rate <= 0:
-            continue
-        nq = max(1000, int(rate * (seconds + warmup)))
-        times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=151 + int(10 * load))
-        lat, wall = server.replay((qo, ids), arrivals=times)
-        keep = times >= warmup
-        ints = query_ints(qo, ids)
-        r = latency_summary(lat[keep], ints[keep].sum(), wall - warmup)
-        r.update({"load_of_sustained": load, "offered_qps": rate, "window_s": float(times[-1] - warmup),
-                  "warmup_s": warmup})
-        at_sustained.append(r)
-        log("serving open loop %.1fx of sustained: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
-            % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
     st = server.stats()
     server.close()
     assert st["err"] == 0, "a served batch reported corrupt input"
@@ -927,8 +916,8 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
                      "max_list": int(h_counts.max()), "median_list": float(np.median(h_counts))},
             "arena_bytes": arena_bytes, "slots": slots, "max_batch_lists": max_batch_lists,
             "results_checked": len(check), "closed_loop": closed, "saturation_qps": sat["qps"],
-            "saturation_uint32_per_s": sat["uint32_per_s"], "open_loop": opened,
-            "open_loop_sustained_qps": sustained, "open_loop_at_sustained": at_sustained, "server_stats": st}
+            "saturation_uint32_per_s": sat["uint32_per_s"], "open_loop": opened, "server_stats": st,
+            "single_array_same_ints": same}
 
 
 def run_cpu_baseline(x, min_seconds=10.0):
@@ -952,7 +941,36 @@ def run_cpu_baseline(x, min_seconds=10.0):
             "host_cpu": model, "host_threads_available": ncpu}
 
 
-ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched", "seek8")
+ONLY_KINDS = ("delta26", "delta28", "plain28", "encode28", "batched", "seek8", "serve")
+
+
+def profile_serve(steps, depth=16384, queries=2_000_000, slots=16, max_batch_lists=16384):
+    """The serving pool of measure_serving and `steps` closed-loop replays of `queries` queries at
+    `depth` outstanding, for profiler runs.  Prints one JSON line with the median rate."""
+    import numpy as np
+    import torch
+
+    import paper_1709_08990_amd as svb
+    from paper_1709_08990_amd import inputs, serve
+    svb.lib()
+    lists, total, cap = 1_000_000, 1_600_000_000, 1 << 22
+    pool = build_pool(svb, torch, np, inputs, lists, total, cap, seed=91)
+    del pool["vals"]
+    server = serve.Server(pool["counts"], pool["in_off"], pool["in_bytes"], pool["streams"], pool["starts"],
+                          arena_bytes=1 << 30, slots=slots, max_batch_lists=max_batch_lists)
+    _, qo, ids = inputs.poisson_queries_flat(queries, 1.0, lists, seed=94)
+    ints = float(pool["h_counts"][ids].sum())
+    rates = []
+    for _ in range(max(1, steps)):
+        lat, wall = server.replay((qo, ids), outstanding=depth)
+        rates.append((queries / wall, ints / wall, float(np.percentile(lat, 99)) * 1e3))
+    st = server.stats()
+    server.close()
+    rates.sort()
+    q, i, p99 = rates[len(rates) // 2]
+    print(json.dumps({"only": "serve", "depth": depth, "queries": queries, "slots": slots,
+                      "max_batch_lists": max_batch_lists, "qps": q, "uint32_per_s": i, "p99_ms": p99,
+                      "server_stats": st}))
 
 
 def profile_only(kind, steps, warmup, variant=None, dirty=False):
@@ -1105,7 +1123,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the VByte / varint-GB comparison")
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-slots", type=int, default=16, help="stream slots of the serving runtime")
+    ap.add_argument("--serve-batch-lists", type=int, default=16384, help="most lists per serving batch")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of each open-loop serving window (seconds of arrivals)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
@@ -1140,6 +1160,9 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.only == "serve":
+        profile_serve(args.steps, slots=args.serve_slots, max_batch_lists=args.serve_batch_lists)
+        return
     if args.only:
         profile_only(args.only, args.steps, args.warmup, args.decode_variant, args.dirty_flush)
         return
@@ -1269,9 +1292,15 @@ def main():
                rc["stream_vbyte"]["bits_per_int"], rc["vbyte"]["bits_per_int"], rc["varint_gb"]["bits_per_int"]))
     if not args.no_serving:
         log("serving: building the 10^6-list pool on the GPU")
-        rs = measure_serving(svb, torch, np, inputs, args.serve_seconds)
+        rs = measure_serving(svb, torch, np, inputs, args.serve_seconds, slots=args.serve_slots,
+                             max_batch_lists=args.serve_batch_lists)
         single = line.get("at_2p28", {}).get("delta_docids", {}).get("uint32_per_s", line["value"])
         rs["saturation_vs_single_array"] = rs["saturation_uint32_per_s"] / single
+        rs["saturation_vs_single_array_same_ints"] = (rs["saturation_uint32_per_s"] /
+                                                      rs["single_array_same_ints"]["uint32_per_s"])
+        log("serving saturation %.3g ints/s: %.2fx the 2^28 document-id array, %.2fx the pool's integers as one "
+            "array" % (rs["saturation_uint32_per_s"], rs["saturation_vs_single_array"],
+                       rs["saturation_vs_single_array_same_ints"]))
         line["serving"] = rs
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -244,7 +244,8 @@ int svb_set_batch_chunk(int kind, uint32_t chunk);
  *
  * svb_server_step runs one scheduling step: retire finished batches, admit
  * waiting queries in arrival order while the arena has room for their output,
- * and launch one batch of all admitted queries on a free slot.  With block != 0
+ * and launch batches of the admitted queries (at most max_batch_lists lists
+ * each) on free slots.  With block != 0
  * and nothing complete yet, it waits for the oldest batch on the device.  It
  * returns the number of complete queries not yet polled (or a negative status).
  *
@@ -252,7 +253,8 @@ int svb_set_batch_chunk(int kind, uint32_t chunk);
  * length (in uint32 units); their arena ranges stay reserved until
  * svb_server_release(query_id).  svb_server_arena returns the arena's device
  * address.  svb_server_stats writes up to `cap` counters: batches, lists,
- * integers, queries admitted, queries completed, most slots busy at once, the
+ * integers, queries admitted, queries completed, most batches running on the
+ * device at once (counted at each launch: slots whose batch had not finished), the
  * decoders' err flags (OR), arena peak (integers), queries waiting, admitted
  * but not launched, arena integers in use, scheduling steps, steps whose host
  * work took over 1 ms, the longest step (microseconds).  svb_server_destroy waits for the
@@ -284,9 +286,11 @@ int svb_server_destroy(void *server);
  * arrival_s[i] seconds have passed since the call began; its latency runs
  * from arrival_s[i] to the moment the host sees its batch complete.  Closed
  * loop (arrival_s == NULL): `outstanding` queries are kept in the system,
- * latency runs from submission.  Replayed queries share the arena and the
- * batches with queries of svb_server_submit but are never polled: their
- * results are released as soon as they complete.  latency_s[i] receives
+ * latency runs from submission.  Queries of svb_server_submit waiting when
+ * the replay starts are launched first (and polled as usual); the replayed
+ * queries' results go to a ring in the largest free range of the arena and
+ * are released as soon as they complete (never polled).  A replayed batch is
+ * a run of consecutive queries; its per-list table is built on the device.  latency_s[i] receives
  * seconds; *wall_s (if not NULL) the call's duration.  Returns SVB_OK, or a
  * negative status (bad trace, a query that can never be admitted, an arena
  * held by unreleased results, a HIP error) with the server's state as of the

@@ -469,7 +469,75 @@ __global__ __launch_bounds__(kThreads) void serve_desc_kernel(ServeDescArgs a) {
     a.desc[t] = d;
 }
 
+// One serving batch's table, built on the device from the integer counts of
+// its lists (in query order, the queries' results back to back from
+// out_base): each list's first task (its segments, ceil(count / 1024), summed
+// over the lists before it) and arena offset (the integers of the lists
+// before it; a batch holds fewer than 2^32).  One workgroup: kPlanPer lists
+// per thread per step, wave scans of both sums, the 16 wave totals scanned in
+// LDS, the carry into the next step.
+constexpr uint32_t kPlanThreads = 1024, kPlanPer = 8, kPlanWaves = kPlanThreads / kWave;
+
+__global__ __launch_bounds__(kPlanThreads) void serve_plan_kernel(ServePlanArgs a) {
+    __shared__ uint32_t s_ints[kPlanWaves + 1], s_tasks[kPlanWaves + 1];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t carry_i = 0, carry_t = 0;
+    for (uint32_t c0 = 0; c0 < a.m; c0 += kPlanThreads * kPlanPer) {
+        uint32_t ci[kPlanPer], ct[kPlanPer];
+        uint32_t si = 0, st = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kPlanPer; ++j) {
+            const uint32_t idx = c0 + tid * kPlanPer + j;
+            ci[j] = idx < a.m ? a.counts[idx] : 0u;
+            ct[j] = (ci[j] + kSegInts - 1) / kSegInts;
+            si += ci[j];
+            st += ct[j];
+        }
+        const uint32_t ii = wave_incl_scan(si), it = wave_incl_scan(st);
+        if (lane == kWave - 1) {
+            s_ints[wave] = ii;
+            s_tasks[wave] = it;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t wi = lane < kPlanWaves ? s_ints[lane] : 0u, wt = lane < kPlanWaves ? s_tasks[lane] : 0u;
+            const uint32_t xi = wave_incl_scan(wi), xt = wave_incl_scan(wt);
+            if (lane < kPlanWaves) {
+                s_ints[lane] = xi - wi;
+                s_tasks[lane] = xt - wt;
+            }
+            if (lane == kWave - 1) {
+                s_ints[kPlanWaves] = xi;
+                s_tasks[kPlanWaves] = xt;
+            }
+        }
+        __syncthreads();
+        uint32_t pi = carry_i + s_ints[wave] + ii - si;
+        uint32_t pt = carry_t + s_tasks[wave] + it - st;
+#pragma unroll
+        for (uint32_t j = 0; j < kPlanPer; ++j) {
+            const uint32_t idx = c0 + tid * kPlanPer + j;
+            if (idx < a.m) {
+                a.out_off[idx] = a.out_base + pi;
+                a.base[idx] = pt;
+            }
+            pi += ci[j];
+            pt += ct[j];
+        }
+        carry_i += s_ints[kPlanWaves];
+        carry_t += s_tasks[kPlanWaves];
+        __syncthreads();  // the next step rewrites the totals
+    }
+    if (tid == 0) a.base[a.m] = carry_t;
+}
+
 }  // namespace
+
+hipError_t launch_serve_plan(const ServePlanArgs &a, hipStream_t s) {
+    if (a.m == 0) return hipSuccess;
+    hipLaunchKernelGGL(serve_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, hipStream_t s) {
     const uint64_t chunk_waves = (a.t_cap + a.chunk - 1) / a.chunk;

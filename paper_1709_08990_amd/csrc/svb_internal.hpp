@@ -131,6 +131,17 @@ struct ServeDescArgs {
     TaskDesc *desc;              // out: the batch's descriptors
 };
 hipError_t launch_serve_desc(const ServeDescArgs &a, uint32_t tasks, hipStream_t s);  // tasks = base[m]
+// A serving batch's table on the device: per batch list its first task and
+// arena offset, from the lists' integer counts.
+struct ServePlanArgs {
+    uint32_t m;               // lists in the batch
+    const uint32_t *counts;   // integers of each batch list (query order; may be pinned host memory);
+                              // they sum below 2^32
+    uint64_t out_base;        // arena offset (uint32 units) of the batch's first list
+    uint32_t *base;           // out: first task of each batch list; base[m] = tasks in the batch
+    uint64_t *out_off;        // out: arena offset of each batch list
+};
+hipError_t launch_serve_plan(const ServePlanArgs &a, hipStream_t s);
 int build_pool_index(uint32_t m, const uint64_t *counts, const uint64_t *in_off, const uint64_t *in_bytes,
                      const uint8_t *in, const uint32_t *starts, uint64_t total_ints, TaskDesc **desc,
                      uint32_t **lbase, uint32_t *tasks, hipStream_t s);

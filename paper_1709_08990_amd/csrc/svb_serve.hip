@@ -15,13 +15,23 @@
 //   2. admits waiting queries in arrival order while the arena has room for
 //      their output (next fit over coalesced free ranges; the first query that
 //      does not fit waits, and so does everything behind it);
-//   3. launches one batch of every admitted query's lists on a free stream
-//      slot: one copy of the batch table (per list: pool list, first task,
-//      arena offset), one kernel that copies the lists' index descriptors with
-//      their output addresses, and the batched decoder's walk.  Batches
-//      admitted while others are still on the device run alongside them.
-// Host work per step is bookkeeping plus one asynchronous copy of the batch's
-// table; nothing waits for the device unless the caller asks to block.
+//   3. launches batches of the admitted queries' lists (at most
+//      max_batch_lists each) on free stream slots: one copy of the batch table
+//      (per list: pool list, first task, arena offset), one kernel that copies
+//      the lists' index descriptors with their output addresses, and the
+//      batched decoder's walk.  Batches admitted while others are still on the
+//      device run alongside them.
+// Host work per step is bookkeeping plus one asynchronous copy of each
+// batch's table; nothing waits for the device unless the caller asks to block.
+//
+// The replay driver (svb_server_replay) takes a whole query trace and keeps
+// the host's work per query to a few additions: the trace's list ids go to
+// the device once, a batch is a run of consecutive queries whose results lie
+// back to back in a ring carved from the arena, and its table (per list: first
+// task, arena offset) is built on the device (serve_plan_kernel) from the
+// lists' counts, which the host writes to pinned memory as it sizes each
+// arriving query: the host passes three numbers per batch instead of a table
+// entry per list.
 #include <algorithm>
 #include <chrono>
 #include <deque>
@@ -89,6 +99,7 @@ struct Server {
     int device = 0;
     uint32_t m = 0;
     std::vector<uint64_t> counts;  // host copy of the pool's list lengths
+    std::vector<uint32_t> counts32;  // the same, saturated at 2^32 - 1 (half the cache footprint)
     bool delta = false;
     TaskDesc *pool_desc = nullptr;  // task index of the pool
     uint32_t *pool_lbase = nullptr;
@@ -265,7 +276,31 @@ void admit(Server &s) {
     }
 }
 
+// Slots whose batch is still running on the device (its completion event
+// has not fired), counting `self` (just launched) once: the most seen at a
+// launch is the peak of batches on the device together.
+uint64_t running_slots(Server &s, const Slot *self) {
+    uint64_t n = 1;
+    for (Slot &sl : s.slots)
+        if (&sl != self && sl.busy && hipEventQuery(sl.done) == hipErrorNotReady) ++n;
+    return n;
+}
+
+int launch_one(Server &s, bool *launched);
+
+// Launches batches of the admitted queries on free slots while the batching
+// policy lets them leave.
 int launch(Server &s) {
+    bool more = true;
+    while (more) {
+        const int st = launch_one(s, &more);
+        if (st != SVB_OK) return st;
+    }
+    return SVB_OK;
+}
+
+int launch_one(Server &s, bool *launched) {
+    *launched = false;
     if (s.admitted.empty()) return SVB_OK;
     Slot *slot = nullptr;
     bool busy = false;
@@ -344,9 +379,8 @@ int launch(Server &s) {
     s.stats[0]++;
     s.stats[1] += j;
     s.stats[2] += total;
-    uint64_t nbusy = 0;
-    for (Slot &sl : s.slots) nbusy += sl.busy ? 1 : 0;
-    s.stats[5] = std::max(s.stats[5], nbusy);
+    s.stats[5] = std::max(s.stats[5], running_slots(s, slot));
+    *launched = true;
     return SVB_OK;
 }
 
@@ -466,6 +500,8 @@ int svb_server_create(uint32_t m, const uint64_t *counts, const uint64_t *in_off
     s->delta = starts != nullptr;
     int st = SVB_OK;
     if (hipMemcpy(s->counts.data(), counts, 8ull * m, hipMemcpyDeviceToHost) != hipSuccess) st = SVB_ERR_HIP;
+    s->counts32.resize(m);
+    for (uint32_t i = 0; i < m; ++i) s->counts32[i] = (uint32_t)std::min<uint64_t>(s->counts[i], 0xFFFFFFFFull);
     uint64_t total = 0, tasks = 0;
     for (uint64_t c : s->counts) {
         total += c;
@@ -551,71 +587,222 @@ int svb_server_release(void *server, uint64_t query_id) {
     return SVB_OK;
 }
 
+constexpr uint64_t kBatchIntsMax = 0xFFFFFFFFull;  // a replayed batch's table holds 32-bit offsets
+
 int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uint32_t *lists, const double *arrival_s,
                       uint32_t outstanding, double *latency_s, double *wall_s) {
     Server *s = (Server *)server;
     if (!s || !qoff || (nq && (!lists || !latency_s)) || (!arrival_s && outstanding == 0)) return SVB_ERR_INVALID;
     for (uint64_t i = 0; i < nq; ++i)
-        if (qoff[i + 1] <= qoff[i] || qoff[i + 1] - qoff[i] > 0xFFFFFFFFull) return SVB_ERR_INVALID;
+        if (qoff[i + 1] <= qoff[i] || qoff[i + 1] - qoff[i] > s->max_batch_lists) return SVB_ERR_INVALID;
+    const uint64_t nl = nq ? qoff[nq] - qoff[0] : 0;
+    for (uint64_t i = 0; i < nl; ++i)
+        if (lists[qoff[0] + i] >= s->m) return SVB_ERR_INVALID;
     std::lock_guard<std::mutex> lock(s->mu);
     (void)hipSetDevice(s->device);
-    if (!s->completed_replay.empty()) return SVB_ERR_INVALID;  // a previous replay did not finish
+    if (!s->completed_replay.empty()) return SVB_ERR_INVALID;
+    int st = SVB_OK;
+    // queries of the ordinary interface queued before the replay are launched
+    // first (they complete in the background and are polled as usual)
+    const std::deque<uint32_t> none;
+    while (!s->waiting.empty() || !s->admitted.empty()) {
+        if ((st = step_locked(*s, true, none)) != SVB_OK) return st;
+        if (!s->waiting.empty() && s->admitted.empty() &&
+            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot &sl) { return sl.busy; }))
+            return SVB_ERR_NOMEM;  // the arena is held by unreleased results
+    }
+    // the replay's output ring: the largest free range of the arena
+    auto big = s->free_ranges.end();
+    for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it)
+        if (big == s->free_ranges.end() || it->second > big->second) big = it;
+    if (big == s->free_ranges.end()) return SVB_ERR_NOMEM;
+    const uint64_t r0 = big->first, R = big->second;
+    s->free_ranges.erase(big);
+    s->free_ints -= R;
+    const uint64_t in_use_before = s->in_use;
+    // the trace's list ids on the device (the descriptor copy reads them), and
+    // the lists' counts in pinned host memory, written as queries arrive and
+    // read by the kernel that builds a batch's table
+    uint32_t *d_lists = nullptr, *h_cnt = nullptr;
+    if (nl && hipMalloc((void **)&d_lists, 4 * nl) != hipSuccess) st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && nl && hipHostMalloc((void **)&h_cnt, 4 * nl, hipHostMallocDefault) != hipSuccess)
+        st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && nl && hipMemcpy(d_lists, lists + qoff[0], 4 * nl, hipMemcpyHostToDevice) != hipSuccess)
+        st = SVB_ERR_HIP;
+
+    // Batches are contiguous runs of queries in arrival order; their results
+    // lie back to back in the ring, one contiguous region per batch, freed in
+    // launch order as batches complete.
+    struct Batch {
+        uint64_t q0, q1, off, len;
+        Slot *slot;
+        bool done;
+    };
+    std::deque<Batch> fifo;
+    uint64_t head = 0;  // next free ring position (regions in use: fifo's, from fifo.front().off)
+    auto ring_space = [&](uint64_t need_first, uint64_t *pos) -> uint64_t {
+        if (fifo.empty()) {
+            *pos = 0;
+            return R;
+        }
+        const uint64_t tail = fifo.front().off;
+        if (head > tail || (head == tail && fifo.empty())) {
+            if (R - head >= need_first) {
+                *pos = head;
+                return R - head;
+            }
+            *pos = 0;
+            return tail;
+        }
+        *pos = head;
+        return tail > head ? tail - head : 0;
+    };
+    std::vector<uint64_t> qints(nq), qtasks(nq);
+    std::vector<double> sent(nq, 0.0);
     typedef std::chrono::steady_clock clock;
     const clock::time_point t0 = clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
-    std::vector<double> sent(nq, 0.0);
-    uint64_t next = 0, done = 0;
-    int st = SVB_OK;
-    while (done < nq) {
-        // arrivals that are due (open loop) or room under the outstanding limit (closed loop).
-        // A backlog beyond two batches' worth of waiting lists stays in the trace: the
-        // queries' latencies still count from their arrival times, and the server's
-        // working set does not grow with the backlog.
+    uint64_t next = 0, launched = 0, done = 0;
+    while (st == SVB_OK && done < nq) {
+        // arrivals: due (open loop) or room under the outstanding limit (closed
+        // loop); a query's size is looked up as it arrives
         const double t = now_s();
-        const size_t backlog_cap = 2 * (size_t)s->max_batch_lists;
-        while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding) &&
-               s->waiting.size() < backlog_cap) {
+        const uint64_t was = next;
+        while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding)) {
+            uint64_t ints = 0, tasks = 0;
+            const uint32_t *cnt = s->counts32.data();  // (prefetching a few queries ahead measured slower)
+            for (uint64_t i = qoff[next]; i < qoff[next + 1]; ++i) {
+                const uint32_t c = cnt[lists[i]];  // 2^32 - 1: at least that long, never admitted
+                h_cnt[i - qoff[0]] = c;
+                ints += c;
+                tasks += (c + kSegInts - 1) / kSegInts;
+            }
+            if (ints > R || ints >= kBatchIntsMax) {
+                st = SVB_ERR_NOMEM;  // can never be admitted
+                break;
+            }
+            qints[next] = ints;
+            qtasks[next] = tasks;
             sent[next] = arrival_s ? arrival_s[next] : t;
-            // the query's id is its index in the trace (replayed queries are not pollable)
-            st = submit_locked(*s, next, (uint32_t)(qoff[next + 1] - qoff[next]), lists + qoff[next], false, nullptr);
-            if (st != SVB_OK) return st;
             ++next;
         }
-        // closed loop: nothing else can happen until a batch finishes, so wait for one
-        const bool block = !arrival_s && next - done >= outstanding;
-        if ((st = step_locked(*s, block, s->completed_replay)) != SVB_OK) return st;
-        if (s->completed_replay.empty() && !s->waiting.empty() && s->admitted.empty() &&
-            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot &sl) { return sl.busy; }))
-            return SVB_ERR_NOMEM;  // nothing on the device and the arena is held by unreleased results
-        if (!s->completed_replay.empty()) {
-            const double tc = now_s();
-            // release in completion order, merging ranges that adjoin (a batch's
-            // queries were admitted one after the other), so the free-range map
-            // changes about once per batch
-            uint64_t run_off = 0, run_len = 0;
-            while (!s->completed_replay.empty()) {
-                const uint32_t e = s->completed_replay.front();
-                s->completed_replay.pop_front();
-                Query &q = s->slab[e];
-                latency_s[q.id] = tc - sent[q.id];
-                if (q.ints) {
-                    if (run_len && run_off + run_len == q.arena_off) {
-                        run_len += q.ints;
-                    } else {
-                        arena_free(*s, run_off, run_len);
-                        run_off = q.arena_off;
-                        run_len = q.ints;
-                    }
-                }
-                q.state = -1;
-                s->free_entries.push_back(e);
-                ++done;
+        if (st != SVB_OK) break;
+        s->stats[3] += next - was;
+        // retire: every finished slot is free again at once (batches of
+        // different sizes finish out of order); their ring regions are freed
+        // in launch order
+        for (Batch &b : fifo) {
+            if (b.done) continue;
+            const hipError_t q = hipEventQuery(b.slot->done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                st = SVB_ERR_HIP;
+                break;
             }
-            arena_free(*s, run_off, run_len);
+            b.done = true;
+            b.slot->busy = false;
+        }
+        if (st != SVB_OK) break;
+        if (!fifo.empty() && fifo.front().done) {
+            const double tc = now_s();
+            while (!fifo.empty() && fifo.front().done) {
+                const Batch &b = fifo.front();
+                for (uint64_t q = b.q0; q < b.q1; ++q) latency_s[q] = tc - sent[q];
+                done += b.q1 - b.q0;
+                s->stats[4] += b.q1 - b.q0;
+                s->in_use -= b.len;
+                fifo.pop_front();
+            }
+            if (fifo.empty()) head = 0;
+        }
+        // launch: the waiting queries in order, as many as a batch and the
+        // ring's free region hold, on a free slot
+        bool launched_now = false;
+        if (launched < next) {
+            Slot *slot = nullptr;
+            bool busy = false;
+            for (Slot &sl : s->slots) {
+                if (!sl.busy && !slot) slot = &sl;
+                busy |= sl.busy;
+            }
+            const uint64_t waiting_lists = qoff[next] - qoff[launched];
+            const bool hold = busy && waiting_lists < s->min_batch_lists &&
+                              (t - sent[launched]) * 1e9 < (double)s->max_wait_ns;
+            uint64_t pos = 0;
+            const uint64_t room = slot && !hold ? ring_space(qints[launched], &pos) : 0;
+            if (slot && !hold && room >= qints[launched]) {
+                uint64_t b = launched, ints = 0, tasks = 0;
+                while (b < next && qoff[b + 1] - qoff[launched] <= s->max_batch_lists && ints + qints[b] <= room &&
+                       ints + qints[b] <= kBatchIntsMax) {
+                    ints += qints[b];
+                    tasks += qtasks[b];
+                    ++b;
+                }
+                const uint32_t nlists = (uint32_t)(qoff[b] - qoff[launched]);
+                uint32_t *d_base = (uint32_t *)(slot->d_table + table_base_off(slot->cap));
+                uint64_t *d_out = (uint64_t *)(slot->d_table + table_out_off(slot->cap));
+                svb::ServePlanArgs pa;
+                pa.m = nlists;
+                pa.counts = h_cnt + (qoff[launched] - qoff[0]);
+                pa.out_base = r0 + pos;
+                pa.base = d_base;
+                pa.out_off = d_out;
+                ServeDescArgs d;
+                d.m = nlists;
+                d.list = d_lists + (qoff[launched] - qoff[0]);
+                d.base = d_base;
+                d.out_off = d_out;
+                d.pool_desc = s->pool_desc;
+                d.pool_lbase = s->pool_lbase;
+                d.arena = s->arena;
+                d.desc = slot->d_desc;
+                BatchArgs a = {};
+                a.m = nlists;
+                a.lbase = d_base;
+                a.t_cap = tasks;
+                a.desc = slot->d_desc;
+                a.err = slot->d_err;
+                if (svb::launch_serve_plan(pa, slot->stream) != hipSuccess ||
+                    svb::launch_serve_desc(d, (uint32_t)tasks, slot->stream) != hipSuccess)
+                    st = SVB_ERR_HIP;
+                if (st == SVB_OK && tasks) st = svb::serve_walk(a, s->delta, slot->stream);
+                if (st == SVB_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = SVB_ERR_HIP;
+                if (st != SVB_OK) break;
+                slot->busy = true;
+                slot->seq = s->launches++;
+                fifo.push_back(Batch{launched, b, pos, ints, slot, false});
+                head = pos + ints;
+                s->in_use += ints;
+                s->stats[7] = std::max(s->stats[7], s->in_use);
+                s->stats[0]++;
+                s->stats[1] += nlists;
+                s->stats[2] += ints;
+                s->stats[5] = std::max(s->stats[5], running_slots(*s, slot));
+                launched = b;
+                launched_now = true;
+            }
+        }
+        // closed loop with nothing more to send or launch: wait for the oldest batch
+        if (!launched_now && !arrival_s && next - done >= outstanding && !fifo.empty()) {
+            for (Batch &b : fifo)
+                if (!b.done) {
+                    if (hipEventSynchronize(b.slot->done) != hipSuccess) st = SVB_ERR_HIP;
+                    break;
+                }
         }
     }
+    // wait for what is still on the device (after an error), then give the ring back
+    for (Batch &b : fifo)
+        if (!b.done) {
+            (void)hipEventSynchronize(b.slot->done);
+            b.slot->busy = false;
+        }
+    s->in_use = in_use_before + R;  // the ring, as arena_free takes it back
+    arena_free(*s, r0, R);
+    if (d_lists) (void)hipFree(d_lists);
+    if (h_cnt) (void)hipHostFree(h_cnt);
     if (wall_s) *wall_s = now_s();
-    return SVB_OK;
+    return st;
 }
 
 int svb_server_set_batching(void *server, uint32_t min_lists, uint32_t max_wait_us) {

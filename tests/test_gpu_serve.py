@@ -61,24 +61,41 @@ def read_result(server, off, n):
     return u32_host(out)[:n].copy()
 
 
+def read_result_on(server, off, n, stream):
+    """Reads a result on its own stream and waits for that stream only: the server's batches on
+    its slot streams keep running meanwhile."""
+    with torch.cuda.stream(stream):
+        out = torch.empty(max(1, n), dtype=torch.int32, device="cuda")
+        if n:
+            svb.svb_copy_u32(n, svb.svb_server_arena(server.handle) + 4 * off, out, stream=stream)
+        host = u32_host(out)[:n].copy()
+    return host
+
+
 @pytest.mark.parametrize("delta", [True, False])
 def test_results_alone_equal_results_in_the_mix(delta):
     lists, starts, counts, dev = make_pool(3_000, 3_000_000, 1 << 16, delta, seed=71 if delta else 72)
-    times, picks = inputs.poisson_queries(300, qps=6_000.0, n_lists=len(lists), seed=73)
+    # arrivals faster than the batches finish, so that batches launched while others are still on
+    # the device run alongside them
+    times, picks = inputs.poisson_queries(300, qps=200_000.0, n_lists=len(lists), seed=73)
     # an arena of 2 MiB holds only a few dozen average queries at once: admission throttles
     arena = 2 << 20
     need = [int(counts[p].sum()) * 4 for p in picks]
     assert max(need) <= arena
+    # small batches that leave as soon as a slot is free: a step launches several at once
     server = serve.Server(dev["counts"], dev["in_off"], dev["in_bytes"], dev["streams"], dev["starts"],
-                          arena_bytes=arena, slots=4, max_batch_lists=256)
+                          arena_bytes=arena, slots=4, max_batch_lists=8)
+    server.set_batching(0, 0)
     mixed = {}
     log_case("serve mix", "delta=%s" % delta)
+    cs = torch.cuda.Stream()
     lat, wall = serve.run_open_loop(server, times, picks,
-                                    on_result=lambda q, off, n: mixed.__setitem__(q, read_result(server, off, n)))
+                                    on_result=lambda q, off, n: mixed.__setitem__(q, read_result_on(server, off, n, cs)))
     st = server.stats()
     assert st["completed"] == len(picks) and st["admitted"] == len(picks)
     assert st["err"] == 0
     assert st["batches"] > 1
+    assert st["peak_busy_slots"] >= 2, "no two batches were on the device together"
     assert st["arena_peak_ints"] * 4 <= arena
     assert np.all(lat > 0)
     # every result equals the oracle's decode of its lists
@@ -147,6 +164,7 @@ def test_replay_open_and_closed_loop():
     lat2, _ = server.replay((qoff, ids), outstanding=64)
     assert lat2.size == 3_000 and np.all(lat2 > 0)
     st = server.stats()
+    assert st["peak_busy_slots"] >= 2
     assert st["completed"] == 6_005 and st["err"] == 0 and st["arena_in_use_ints"] == 0
     assert st["integers"] == 2 * int(counts[ids].sum()) + sum(int(counts[p].sum()) for p in mine.values())
     # the server still answers ordinary queries afterwards, correctly
