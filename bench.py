@@ -81,7 +81,8 @@ def log(msg):
 
 # Sources the dominant kernel (the delta decode pass) is built from: a change
 # to any of them voids the stored counter figures.
-DIGEST_FILES = ("svb_decode.hip", "svb_segment.hpp", "svb_device.hpp", "svb_internal.hpp")
+DIGEST_FILES = ("svb_decode.hip", "svb_delta.hip", "svb_scan.hip", "svb_segment.hpp", "svb_device.hpp",
+                "svb_internal.hpp")
 
 
 def source_digest():
@@ -1215,6 +1216,7 @@ def main():
                      "whole_call": {"ms": r["ms_per_call"], "GBps": r["call_GBps"],
                                     "frac": r["call_frac_of_peak"]}},
         "kernels_ms": r["kernels_ms"],
+        "timed_region_s": r["protocol"]["timed_region_s"],
         "protocol": r["protocol"],
         "dirty_flush": r["dirty_flush"],
         "unflushed": r["unflushed"],

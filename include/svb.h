@@ -78,7 +78,10 @@ enum svb_status {
 /* ceil(n/4): size of the control stream (Section 4). */
 uint64_t svb_control_bytes(uint64_t n);
 
-/* ceil(n/4) + 4n: the largest stream n integers can need (every L_i = 4). */
+/* ceil(n/4) + 4n: the largest stream n integers can need.  Section 3 gives
+ * each integer a byte length of 1 to 4 (4 for values of 2^24 and above), and
+ * the layout of Section 4 stores one control byte per 4 integers followed by
+ * the integers' bytes, so the worst case is every integer 4 bytes long. */
 uint64_t svb_max_compressed_bytes(uint64_t n);
 
 /*
@@ -423,11 +426,19 @@ int svb_select_batch(void *index, uint32_t q, const uint32_t *list, const uint64
                      uint32_t *err, void *stream);
 int svb_seek_index_destroy(void *index);
 
-/* Message for a status code (static string). */
+/* Message for a status code (static string).  A support call of this
+ * library's interface: the paper defines no error reporting, so the codes
+ * above are this library's own (a corrupt stream is the one condition that
+ * the format itself can present, Section 4's length code read past the
+ * data bytes). */
 const char *svb_strerror(int status);
 
 /* Frees every scratch workspace the library holds (all devices and streams).
- * Synchronises the devices first.  Later calls allocate again. */
+ * Synchronises the devices first.  Later calls allocate again.  A support
+ * call of this library's interface: the scratch holds the per-group byte
+ * counts, offsets and value sums that turn the serial pointer advance and
+ * running sum of Sections 2 and 4 into scans; the paper's decoder, a single
+ * pass in registers, needs none. */
 void svb_release_workspace(void);
 
 /*

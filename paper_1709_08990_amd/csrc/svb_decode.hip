@@ -108,6 +108,16 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 // memory-side cache when the decode starts (measured at 2^28 document ids:
 // 0.385 ms per call against 0.400 front to back; no change at 2^26, whose
 // whole stream stays cached either way).
+// Segments a wave keeps in flight (walker depth).  Measured at 2^28: plain
+// decode of the stress integers 0.310 ms at depth 2 (3 waves per SIMD) and
+// 0.311 at depth 1 (5 waves per SIMD); delta decode of the document ids
+// 0.315 ms at depth 1, 0.328 at depth 2.
+#ifndef SVB_PLAIN_DEPTH
+#define SVB_PLAIN_DEPTH 2
+#endif
+#ifndef SVB_DELTA_DEPTH
+#define SVB_DELTA_DEPTH 1
+#endif
 #ifndef SVB_DECODE_REVERSE
 #define SVB_DECODE_REVERSE 1
 #endif
@@ -124,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const ui
     const uint64_t s0 = g * kGroupSegs;
     const uint64_t s_end = s0 + kGroupSegs < segs ? s0 + kGroupSegs : segs;
     uint32_t carry = (MODE == kDelta) ? p.gvpre[g] : 0u;
-    Walker<MODE == kPlain ? 2 : 1> w;  // plain decoding waits on memory: two segments in flight
+    Walker<MODE == kPlain ? SVB_PLAIN_DEPTH : SVB_DELTA_DEPTH> w;
     walker_begin(p, w, s0, s_end, goff32 ? (uint64_t)goff32[g] : p.goff[g], lane);
     for (uint64_t s = s0; s < s_end; ++s) {
         SegPlan seg;
