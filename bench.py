@@ -69,7 +69,7 @@ WORKLOAD = ("delta decode of 2^26 sorted uint32 document ids: gaps Geometric(1/8
             "w.p. 0.99, uniform in [2^8, 2^20) w.p. 0.01, running sum wrapping mod 2^32, start 0")
 N_HEAD = 1 << 26
 COPY_WORDS = 1 << 26                     # 256 MiB copied by the ceiling / counter-scaling copy
-COUNTERS_FILE = "counters_decode_delta_docids_2p26.md"
+COUNTERS_FILE = "counters_delta_decode_docids_2p26.md"
 DOMINANT_SYMBOL = "decode_kernel<1, false>"  # rocprofv3 name fragment of the delta decode pass (general variant)
 COPY_SYMBOL = "copy_kernel"
 
@@ -243,6 +243,14 @@ def summarize_pmc(out_md, title, commands, paths, only=None):
             fmt = lambda v: "%.2f" % (v / 1e6) if v is not None else "-"
             lines.append("| `%s` | %d | %.1f | %s | %s | %s |" % (_short(k), len(dur[k]), med(k), fmt(fb), fmt(wb),
                                                                  "%.0f" % gb if gb is not None else "-"))
+        dom = [k for k in names if DOMINANT_SYMBOL in k and mean(k, "FETCH_SIZE") is not None
+               and mean(k, "WRITE_SIZE") is not None]
+        if dom:
+            k = dom[0]
+            lines += ["", "traffic_bytes_per_launch: %.0f" % (1024 * (mean(k, "FETCH_SIZE") * scale.get("FETCH_SIZE", 1)
+                                                                      + mean(k, "WRITE_SIZE") * scale.get("WRITE_SIZE", 1))),
+                      "(of `%s`, the bench line's dominant kernel: read by bench.py as roofline.traffic while the "
+                      "source digest below matches)" % _short(k)]
     sq = [c for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
                       "SQ_WAIT_INST_ANY") if any(per[k].get(c) for k in names)]
     if sq and any(per[k].get("SQ_WAVES") for k in names):
