@@ -149,8 +149,24 @@ int serve_walk(BatchArgs &a, bool delta, hipStream_t s);
 
 // Seek and select over a task index (built by build_pool_index): per task the
 // running maximum of its list's values up to the task's segment's end.
+// Per list, what a query of a short list needs in one 64-byte line: its
+// stream, its length, its first task and segment count, the running sum it
+// starts from and its largest value.
+struct alignas(64) SeekList {
+    uint64_t in;        // the list's stream
+    uint64_t in_bytes;  // bytes of it
+    uint64_t n;         // integers
+    uint32_t first;     // first task in the index
+    uint32_t segs;      // segments
+    uint32_t carry;     // delta lists: the start value
+    uint32_t top;       // the running maximum at the list's end (0 for an empty list)
+    uint32_t pad[6];
+};
+static_assert(sizeof(SeekList) == 64, "one line per list");
+
 struct SeekArgs {
     uint32_t m;               // lists
+    SeekList *lists;          // per list (written by the index build)
     uint64_t tasks;           // segments of the index
     const TaskDesc *desc;     // task index (no output addresses)
     const uint32_t *lbase;    // first task of each list; lbase[m] = tasks

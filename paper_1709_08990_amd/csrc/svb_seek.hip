@@ -225,6 +225,25 @@ __global__ __launch_bounds__(kThreads) void run_max_kernel(SeekArgs a) {
     }
 }
 
+// Index build, pass 3: one line per list (one thread each).
+__global__ __launch_bounds__(kThreads) void list_rec_kernel(SeekArgs a) {
+    const uint32_t l = blockIdx.x * kThreads + threadIdx.x;
+    if (l >= a.m) return;
+    const uint32_t first = a.lbase[l], segs = a.lbase[l + 1] - first;
+    SeekList r = {};
+    r.first = first;
+    r.segs = segs;
+    if (segs) {
+        const TaskDesc &d = a.desc[first];
+        r.in = d.in;
+        r.in_bytes = d.in_bytes;
+        r.n = d.n;
+        r.carry = d.carry;
+        r.top = a.rmax[first + segs - 1];
+    }
+    a.lists[l] = r;
+}
+
 // Marks query `qi` as refused.
 __device__ __forceinline__ void refuse(const SeekArgs &a, uint32_t qi, uint32_t code, uint32_t lane) {
     if (lane != 0) return;
@@ -360,14 +379,220 @@ __device__ __forceinline__ void answer(const SeekArgs &a, uint32_t qi, uint8_t *
     }
 }
 
+// Four queries per wave, 16 lanes each, for lists of at most 256 integers
+// (one segment of one row: 64 control bytes).  Lane g of a group takes
+// control bytes 4 g .. 4 g + 3 (16 integers): the lengths, a 16-lane scan of
+// the byte counts (DPP row shifts stay inside a row of 16 lanes), the row's
+// data bytes staged in the group's quarter of the wave's LDS area, the
+// integers cut out with two byte-align instructions each, the running sum
+// for delta lists (in the lane, then across the group).  A query whose list
+// has more than one segment, or more than 256 integers, is left to the
+// one-wave path: the return value says which groups answered.
+constexpr uint32_t kGroupLanes = 16;
+constexpr uint32_t kRowCtrl = 64, kRowInts = 4 * kRowCtrl;
+constexpr uint32_t kGroupStage = kStageBytes / (kWave / kGroupLanes);  // 1056: 1024 data bytes, 15 before, 8 after
+static_assert(kGroupStage >= 4 * kRowInts + 16 + 16, "a group's staging area holds a row's data bytes");
+
+__device__ __forceinline__ uint32_t row16_incl_scan(uint32_t x) {
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    return x;
+}
+
+template <bool SEEK>
+__device__ __forceinline__ bool answer_rows4(const SeekArgs &a, uint64_t qi, bool active, uint8_t *stage,
+                                             uint32_t lane) {
+    const uint32_t gl = lane & (kGroupLanes - 1);
+    const uint32_t gbase = lane & ~(kGroupLanes - 1);
+    uint8_t *gs = stage + (lane / kGroupLanes) * kGroupStage;
+    if (!active) return true;
+    const uint32_t l = a.list[qi];
+    const uint32_t t_raw = SEEK ? a.target[qi] : 0u;
+    const uint64_t idx = SEEK ? 0ull : a.idx[qi];
+    if (l >= a.m) {
+        if (gl == 0) refuse(a, (uint32_t)qi, SVB_QUERY_OUT_OF_RANGE, 0);
+        return true;
+    }
+    const SeekList &rec = a.lists[l];
+    const uint32_t segs = rec.segs;
+    if (segs == 0) {
+        // an empty list: a seek answers position 0, a select is out of range
+        if (gl == 0) {
+            if (SEEK) {
+                a.pos[qi] = 0ull;
+                a.value[qi] = 0u;
+            } else {
+                refuse(a, (uint32_t)qi, SVB_QUERY_OUT_OF_RANGE, 0);
+            }
+        }
+        return true;
+    }
+    if (segs != 1) return false;
+    const uint64_t n = rec.n;
+    if (n > kRowInts) return false;
+    const uint8_t *in = (const uint8_t *)rec.in;
+    const uint64_t in_bytes = rec.in_bytes;
+    const uint32_t carry = rec.carry;
+    if (SEEK) {
+        if (rec.top < t_raw) {
+            // no value reaches the target: the list's length
+            if (gl == 0) {
+                a.pos[qi] = n;
+                a.value[qi] = 0u;
+            }
+            return true;
+        }
+    } else if (idx >= n) {
+        if (gl == 0) refuse(a, (uint32_t)qi, SVB_QUERY_OUT_OF_RANGE, 0);
+        return true;
+    }
+    // the lane's four control bytes, codes of integers past n cleared
+    const uint32_t nblocks = (uint32_t)((n + 3) >> 2);
+    uint32_t c[4], m[4], bytes = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t b = 4 * gl + k;
+        const int32_t left = (int32_t)n - (int32_t)(4 * b);
+        m[k] = left <= 0 ? 0u : (left >= 4 ? 4u : (uint32_t)left);
+        const uint32_t raw = b < nblocks ? (uint32_t)gptr(in)[b] : 0u;
+        c[k] = m[k] ? (raw & ((1u << (2 * m[k])) - 1u)) : 0u;
+        bytes += m[k] + __builtin_popcount(c[k]) + __builtin_popcount(c[k] & 0xAAu);
+    }
+    const uint32_t incl = row16_incl_scan(bytes);
+    const uint32_t total = (uint32_t)__shfl((int)incl, (int)(gbase + kGroupLanes - 1));
+    if (total > in_bytes - nblocks) {  // the index build checked in_bytes >= nblocks
+        if (gl == 0) refuse(a, (uint32_t)qi, SVB_DECODE_CORRUPT, 0);
+        return true;
+    }
+    // the row's data bytes (the whole data stream of a list of one segment)
+    // into the group's staging area, 16-byte chunks from the aligned address
+    // below the first
+    const uint8_t *q0 = in + nblocks;
+    const uint32_t sh16 = (uint32_t)((uintptr_t)q0 & 15u);
+    const uint8_t *abase = q0 - sh16;
+    const uint32_t nch = (sh16 + total + 15) >> 4;
+    const uint8_t *lo = in, *hi = in + in_bytes;
+#pragma unroll
+    for (uint32_t i = 0; i < (kGroupStage - 16) / (16 * kGroupLanes) + 1; ++i) {
+        const uint32_t ch = gl + kGroupLanes * i;
+        if (ch < nch) {
+            const uint8_t *cp = abase + 16 * ch;
+            u32x4a w = u32x4a{0u, 0u, 0u, 0u};
+            if (cp < hi && cp + 16 > lo) w = *gptr((const u32x4a *)cp);
+            *(u32x4a *)(gs + 16 * ch) = w;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the lane's 16 integers, cut from the staged bytes in two passes (no
+    // array of them: a wave of this kernel holds few registers): the first
+    // sums them (delta lists), the second runs the values and keeps the one
+    // the query asks for
+    const uint32_t *w32 = (const uint32_t *)gs;
+    const uint32_t q_lane = sh16 + incl - bytes;
+    auto int_at = [&](uint32_t &q, uint32_t k, uint32_t j, bool &valid) -> uint32_t {
+        const uint32_t L = ((c[k] >> (2 * j)) & 3u) + 1u;
+        valid = j < m[k];
+        const uint32_t x = __builtin_amdgcn_alignbyte(w32[(q >> 2) + 1], w32[q >> 2], q & 3u);
+        q += valid ? L : 0u;
+        return valid ? (L == 4 ? x : x & ((1u << (8 * L)) - 1u)) : 0u;
+    };
+    // sixteen one-byte integers (every control byte of the lane zero, none
+    // past n, as on lists of small differences): the lane's 16 data bytes,
+    // cut from five aligned dwords, summed by SAD and unpacked by bit-field
+    // extracts; otherwise integer by integer
+    const bool zc = (c[0] | c[1] | c[2] | c[3]) == 0 && m[0] + m[1] + m[2] + m[3] == 16;
+    uint32_t X[4] = {0u, 0u, 0u, 0u};
+    uint32_t run = 0;
+    if (zc) {
+        const uint32_t d = q_lane >> 2, o = q_lane & 3u;
+        uint32_t prev = w32[d];
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t nxt = w32[d + 1 + i];
+            X[i] = __builtin_amdgcn_alignbyte(nxt, prev, o);
+            prev = nxt;
+        }
+    }
+    if (a.delta) {
+        uint32_t sum = 0;
+        if (zc) {
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) sum = __builtin_amdgcn_sad_u8(X[i], 0u, sum);
+        } else {
+            uint32_t q = q_lane;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    bool valid;
+                    sum += int_at(q, k, j, valid);
+                }
+        }
+        run = carry + row16_incl_scan(sum) - sum;  // the running value before the lane's first integer
+    }
+    // SEEK: the lane's first valid value >= target (jf = 16 if none); select:
+    // the value at idx, held by lane idx / 16
+    const uint32_t jsel = SEEK ? 16u : (uint32_t)(idx & 15u);
+    uint32_t jf = 16, mine = 0;
+    auto visit = [&](uint32_t i, uint32_t x, bool valid) {
+        const uint32_t vv = a.delta ? (run += x) : x;
+        if (SEEK) {
+            if (jf == 16 && valid && vv >= t_raw) {
+                jf = i;
+                mine = vv;
+            }
+        } else if (i == jsel) {
+            mine = vv;
+        }
+    };
+    if (zc) {
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i) visit(i, __builtin_amdgcn_ubfe(X[i >> 2], 8 * (i & 3u), 8), true);
+    } else {
+        uint32_t q = q_lane;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                bool valid;
+                const uint32_t x = int_at(q, k, j, valid);
+                visit(4 * k + j, x, valid);
+            }
+    }
+    uint32_t pos, val;
+    if (SEEK) {
+        // the row holds a value >= target: the first lane of the group with one
+        const uint64_t mask = (__ballot(jf < 16) >> gbase) & 0xFFFFull;
+        const uint32_t owner = mask ? (uint32_t)__builtin_ctzll(mask) : 0u;
+        const uint32_t ojf = (uint32_t)__shfl((int)jf, (int)(gbase + owner));
+        val = (uint32_t)__shfl((int)mine, (int)(gbase + owner));
+        pos = 16 * owner + ojf;
+    } else {
+        val = (uint32_t)__shfl((int)mine, (int)(gbase + (uint32_t)(idx >> 4)));
+        pos = (uint32_t)idx;
+    }
+    if (gl == 0) {
+        if (SEEK) a.pos[qi] = pos;
+        a.value[qi] = val;
+    }
+    return true;
+}
+
 // Each wave answers a run of a.chunk consecutive queries, so that a large
 // batch does not cost one workgroup launch per four queries.  Throughput
 // follows the number of resident waves (each query is a chain of dependent
 // loads), so the kernel is held to eight waves per SIMD.  (Keeping the next
 // queries' index loads in flight while one decodes was measured no faster:
 // it cost more registers, hence waves, than it saved in waiting.)
+#ifndef SVB_QUERY_WPE
+#define SVB_QUERY_WPE 6
+#endif
 template <bool SEEK>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void query_kernel(SeekArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SVB_QUERY_WPE, 8))) void query_kernel(SeekArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -375,12 +600,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))
     const uint64_t q1 = q0 + a.chunk < a.q ? q0 + a.chunk : a.q;
     uint8_t *stage = s_stage + wave * kStageBytes;
 #pragma unroll 1
-    for (uint64_t qi = q0; qi < q1; ++qi) {
-        answer<SEEK>(a, (uint32_t)qi, stage, lane);
-        // the next query overwrites the staging area: LDS operations of a wave
-        // complete in order
+    for (uint64_t qb = q0; qb < q1; qb += kWave / kGroupLanes) {
+        // four queries at once, 16 lanes each; the ones that need a whole wave after
+        const uint64_t qi = qb + lane / kGroupLanes;
+        const bool done = answer_rows4<SEEK>(a, qi, qi < q1, stage, lane);
+        const uint64_t rest = __ballot(!done);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        for (uint32_t g = 0; g < kWave / kGroupLanes; ++g) {
+            if (!((rest >> (kGroupLanes * g)) & 1ull)) continue;
+            answer<SEEK>(a, (uint32_t)(qb + g), stage, lane);
+            // the next query overwrites the staging area: LDS operations of a
+            // wave complete in order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 }
 
@@ -392,6 +626,9 @@ hipError_t launch_seek_index(const SeekArgs &a, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(run_max_kernel, dim3((a.m + kWaves - 1) / kWaves), dim3(kThreads), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(list_rec_kernel, dim3((a.m + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -420,6 +657,7 @@ struct SeekIndex {
     svb::TaskDesc *desc = nullptr;
     uint32_t *lbase = nullptr;
     uint32_t *rmax = nullptr;
+    svb::SeekList *lists = nullptr;
 };
 
 void free_index(SeekIndex *x) {
@@ -431,6 +669,7 @@ void free_index(SeekIndex *x) {
     if (x->desc) (void)hipFree(x->desc);
     if (x->lbase) (void)hipFree(x->lbase);
     if (x->rmax) (void)hipFree(x->rmax);
+    if (x->lists) (void)hipFree(x->lists);
     (void)hipSetDevice(cur);
     delete x;
 }
@@ -453,10 +692,12 @@ int queries(void *index, uint32_t q, const uint32_t *list, const uint32_t *targe
     a.desc = x->desc;
     a.lbase = x->lbase;
     a.rmax = x->rmax;
+    a.lists = x->lists;
     a.delta = x->delta;
     a.q = q;
-    // queries per wave: one while that still leaves tens of thousands of waves
-    a.chunk = std::min<uint32_t>(16u, std::max<uint32_t>(1u, q / 32768u));
+    // queries per wave: four (one per 16-lane group) while that still leaves
+    // tens of thousands of waves, up to 16
+    a.chunk = std::min<uint32_t>(16u, std::max<uint32_t>(4u, (q / 32768u) & ~3u));
     a.list = list;
     a.target = target;
     a.idx = idx;
@@ -485,6 +726,8 @@ int svb_seek_index_create(uint32_t m, const uint64_t *counts, const uint64_t *in
     uint32_t *d_err = nullptr;
     if (st == SVB_OK && hipMalloc((void **)&x->rmax, 4ull * (x->tasks ? x->tasks : 1)) != hipSuccess)
         st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && hipMalloc((void **)&x->lists, sizeof(svb::SeekList) * (m ? m : 1)) != hipSuccess)
+        st = SVB_ERR_NOMEM;
     if (st == SVB_OK && hipMalloc((void **)&d_err, 4) != hipSuccess) st = SVB_ERR_NOMEM;
     uint32_t h_err = 0;
     if (st == SVB_OK) {
@@ -494,6 +737,7 @@ int svb_seek_index_create(uint32_t m, const uint64_t *counts, const uint64_t *in
         a.desc = x->desc;
         a.lbase = x->lbase;
         a.rmax = x->rmax;
+        a.lists = x->lists;
         a.delta = x->delta;
         a.err = d_err;
         if (svb::launch_fill(d_err, 1, 0u, s) != hipSuccess || svb::launch_seek_index(a, s) != hipSuccess ||
