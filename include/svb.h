@@ -205,16 +205,22 @@ int svb_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
 
 /*
  * Autotuning of the batched calls: the number of consecutive tasks a wave
- * takes (1, 2, 4, 8 or 16 segments of 1024 integers) is chosen per device and
- * per kind of call (decode or encode, plain or delta).
+ * takes (1, 2, 4, 8 or 16 segments of 1024 integers) and, for decoding, the
+ * schedule (static: wave w takes tasks w chunk .. (w + 1) chunk - 1; work
+ * queue, chunk | SVB_BATCH_QUEUE: a grid of a few waves per SIMD, each
+ * grabbing the next chunk of tasks from a device counter until none are
+ * left) are chosen per device and per kind of call (decode or encode, plain
+ * or delta).
  * svb_autotune_decode_batch times each candidate on the given batch (the
  * arguments of svb_decode_batch; it decodes the batch several times and
  * synchronises the stream), keeps the fastest for later calls of that kind on
  * the current device, and writes it to *chunk.  svb_autotune_encode_batch
  * does the same for encoding.  svb_set_batch_chunk(kind, chunk) sets the
- * choice directly; kind = 2 * (encode ? 1 : 0) + (delta ? 1 : 0).  The
- * default is 4.
+ * choice directly; kind = 2 * (encode ? 1 : 0) + (delta ? 1 : 0); the queue
+ * bit is refused for encoding kinds.  The default is 4 (static).  Serving
+ * batches use the tuned chunk on the static schedule.
  */
+#define SVB_BATCH_QUEUE 0x100u
 int svb_autotune_decode_batch(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
                               const uint64_t *in_bytes, const uint8_t *in, const uint64_t *out_off,
                               uint32_t *out, const uint32_t *starts, uint64_t total_ints, uint32_t *err,

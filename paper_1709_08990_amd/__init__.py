@@ -230,8 +230,12 @@ def svb_autotune_encode_batch(m, counts, in_off, inp, out_off, out, out_bytes=No
     return int(chosen.value)
 
 
+SVB_BATCH_QUEUE = 0x100
+
+
 def svb_set_batch_chunk(kind, chunk):
-    """kind = 2 * encode + delta; chunk (consecutive tasks per wave) in {1, 2, 4, 8, 16}."""
+    """kind = 2 * encode + delta; chunk (consecutive tasks per wave) in {1, 2, 4, 8, 16}, or for
+    decoding chunk | SVB_BATCH_QUEUE (the work-queue schedule)."""
     return _check(lib().svb_set_batch_chunk(int(kind), int(chunk)), "svb_set_batch_chunk")
 
 

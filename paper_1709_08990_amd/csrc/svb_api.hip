@@ -377,9 +377,14 @@ int do_append(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint64_t k, cons
 // Tasks (segments) per wave of the main pass, per (device, kind); kind = 2 encode + delta.
 std::map<std::pair<int, int>, uint32_t> g_chunk;
 constexpr uint32_t kDefaultChunk = 4;
+constexpr uint32_t kQueueBit = SVB_BATCH_QUEUE;  // the decode walk's work-queue schedule
 constexpr uint32_t kChunkChoices[] = {1, 2, 4, 8, 16};
+constexpr uint32_t kQueueChoices[] = {kQueueBit | 1, kQueueBit | 2, kQueueBit | 4, kQueueBit | 8};
 
-bool valid_chunk(uint32_t c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
+bool valid_chunk(uint32_t c) {
+    const uint32_t k = c & ~kQueueBit;
+    return k == 1 || k == 2 || k == 4 || k == 8 || k == 16;
+}
 
 uint32_t tuned_chunk(int kind) {
     int dev = 0;
@@ -403,7 +408,7 @@ struct BatchCall {
 
 // Scratch layout of a batched call over at most T tasks and M lists.
 struct BatchLayout {
-    uint64_t o_litems, o_lbase, o_ilist, o_ifirst, o_ibytes, o_ioff, o_ivsum, o_ivpre, o_desc, o_scan, need;
+    uint64_t o_litems, o_lbase, o_ilist, o_ifirst, o_ibytes, o_ioff, o_ivsum, o_ivpre, o_desc, o_queue, o_scan, need;
 };
 
 BatchLayout batch_layout(uint64_t M, uint64_t T) {
@@ -418,7 +423,8 @@ BatchLayout batch_layout(uint64_t M, uint64_t T) {
     L.o_ivsum = L.o_ioff + up16(8 * T);
     L.o_ivpre = L.o_ivsum + up16(4 * T);
     L.o_desc = (L.o_ivpre + up16(4 * T) + 63) & ~63ull;
-    L.o_scan = L.o_desc + 64 * T;
+    L.o_queue = L.o_desc + 64 * T;
+    L.o_scan = L.o_queue + 16;
     L.need = L.o_scan + up16(std::max(scan_scratch_bytes(M), scan_scratch_bytes(T)));
     return L;
 }
@@ -465,7 +471,8 @@ int prepare_batch(const BatchCall &c, uint32_t C, uint64_t T, uint8_t *sc, Batch
     a.item_list = (uint32_t *)(sc + L.o_ilist);
     a.item_first = (uint32_t *)(sc + L.o_ifirst);
     a.t_cap = (uint32_t)T;
-    a.chunk = C;
+    a.chunk = C & ~kQueueBit;
+    a.queue = (C & kQueueBit) && !c.encode ? (uint32_t *)(sc + L.o_queue) : nullptr;
     a.ibytes = (uint32_t *)(sc + L.o_ibytes);
     a.ioff = (uint64_t *)(sc + L.o_ioff);
     a.ivsum = (uint32_t *)(sc + L.o_ivsum);
@@ -494,6 +501,7 @@ int prepare_batch(const BatchCall &c, uint32_t C, uint64_t T, uint8_t *sc, Batch
              }))) != SVB_OK)
             return st;
     }
+    if (a.queue && (st = hip_status(launch_fill(a.queue, 1, 0u, s))) != SVB_OK) return st;
     // descriptors last: for delta decoding they carry each task's running sum
     return run("batch_desc", kBatchDesc);
 }
@@ -532,7 +540,10 @@ int autotune_batch(const BatchCall &c, uint32_t *chosen, void *stream) {
     uint32_t best = kDefaultChunk;
     float best_ms = 1e30f;
     int st = SVB_OK;
-    for (uint32_t g : kChunkChoices) {
+    // static chunks for every call; the work-queue schedule for decoding
+    std::vector<uint32_t> choices(std::begin(kChunkChoices), std::end(kChunkChoices));
+    if (!c.encode) choices.insert(choices.end(), std::begin(kQueueChoices), std::end(kQueueChoices));
+    for (uint32_t g : choices) {
         for (int warm = 0; warm < 2 && st == SVB_OK; ++warm) st = do_batch(c, g, stream);
         if (st != SVB_OK) break;
         constexpr int kReps = 5;
@@ -630,8 +641,9 @@ int build_pool_index(uint32_t m, const uint64_t *counts, const uint64_t *in_off,
 int serve_walk(BatchArgs &a, bool delta, hipStream_t s) {
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        a.chunk = tuned_chunk(delta ? 1 : 0);
+        a.chunk = tuned_chunk(delta ? 1 : 0) & ~kQueueBit;  // a serving batch walks on the static schedule
     }
+    a.queue = nullptr;
     return hip_status(launch_batch(a, kBatchWork, false, delta, s));
 }
 
@@ -876,7 +888,7 @@ int svb_autotune_encode_batch(uint32_t m, const uint64_t *counts, const uint64_t
 }
 
 int svb_set_batch_chunk(int kind, uint32_t chunk) {
-    if (kind < 0 || kind > 3 || !valid_chunk(chunk)) return SVB_ERR_INVALID;
+    if (kind < 0 || kind > 3 || !valid_chunk(chunk) || ((chunk & kQueueBit) && kind >= 2)) return SVB_ERR_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SVB_ERR_HIP;
     std::lock_guard<std::mutex> lock(g_mu);

@@ -176,27 +176,16 @@ __device__ __forceinline__ void issue_task(const TaskHdr &k, const SegCtrl &sc, 
     span_load(k.p, pd.sp, lane);
 }
 
-// Walks tasks [t0, t0 + chunk) of the task list with a pipeline three tasks
+// Walks tasks [t0, t_end) of the task list with a pipeline three tasks
 // deep: in the iteration that decodes task t, the data of t + 1, the control
 // bytes of t + 2 and the descriptor of t + 3 are requested, each from what the
 // previous iteration loaded.
 // kPlain / kDelta: decode and store (delta: running sum from the task's
-// carry).  Five waves per SIMD: the delta walk fits 96 registers without spilling, and
-// was measured 12% faster there than at four.
+// carry).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_walk_kernel(BatchArgs a) {
-    static_assert(MODE == kPlain || MODE == kDelta, "the value sums walk in runs (batch_sums_runs_kernel)");
+__device__ __forceinline__ void walk_tasks(const BatchArgs &a, uint64_t t0, uint64_t t_end, uint8_t *stage,
+                                           uint32_t lane, bool &corrupt) {
     constexpr bool DELTA = MODE == kDelta;
-    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint32_t total = task_total(a);
-    const uint64_t t0 = ((uint64_t)blockIdx.x * kWaves + wave) * a.chunk;
-    if (t0 >= total) return;
-    const uint64_t t_end = t0 + a.chunk < total ? t0 + a.chunk : total;
-    uint8_t *stage = s_stage + wave * kStageBytes;
-    bool corrupt = false;
-
     auto active = [&](const TaskHdr &k) { return k.valid; };
     TaskHdr h0 = load_hdr(a, t0, t_end);
     Pending pend;
@@ -238,6 +227,40 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
         h1 = h2;
         h2 = h3;
         c1 = c2;
+    }
+}
+
+// The decode walk.  Static schedule: wave w takes tasks [w chunk, (w + 1)
+// chunk).  Work queue (a.queue set): a grid of a few waves per SIMD, each
+// wave grabbing the next `chunk` tasks from a device counter until none are
+// left.  Five waves per SIMD: the delta walk fits 96 registers without
+// spilling, and was measured 12% faster there than at four.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_walk_kernel(BatchArgs a) {
+    static_assert(MODE == kPlain || MODE == kDelta, "the value sums walk in runs (batch_sums_runs_kernel)");
+    __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t total = task_total(a);
+    uint8_t *stage = s_stage + wave * kStageBytes;
+    bool corrupt = false;
+    if (a.queue) {
+#pragma unroll 1
+        for (;;) {
+            uint32_t t0 = 0;
+            if (lane == 0) t0 = atomicAdd(a.queue, a.chunk);
+            t0 = __builtin_amdgcn_readfirstlane(t0);
+            if (t0 >= total) break;  // every wave reaches this once the counter passes the last task
+            const uint64_t t_end = (uint64_t)t0 + a.chunk < total ? (uint64_t)t0 + a.chunk : total;
+            walk_tasks<MODE>(a, t0, t_end, stage, lane, corrupt);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else {
+        const uint64_t t0 = ((uint64_t)blockIdx.x * kWaves + wave) * a.chunk;
+        if (t0 >= total) return;
+        const uint64_t t_end = t0 + a.chunk < total ? t0 + a.chunk : total;
+        walk_tasks<MODE>(a, t0, t_end, stage, lane, corrupt);
     }
     if (corrupt && a.err && lane == 0) *a.err = SVB_DECODE_CORRUPT;
 }
@@ -443,6 +466,7 @@ __global__ __launch_bounds__(kThreads) void batch_encode_kernel(BatchArgs a) {
 }
 
 uint32_t list_grid(uint32_t m) { return (m + kThreads - 1) / kThreads; }
+constexpr uint64_t kQueueWaves = 256 * 4 * 5;
 uint32_t wave_grid(uint64_t waves) { return (uint32_t)((waves + kWaves - 1) / kWaves); }
 
 // ---------------------------------------------------------------- serving
@@ -580,10 +604,12 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
                 else
                     hipLaunchKernelGGL((batch_encode_kernel<false>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
             } else {
+                // with a work queue: at most five waves per SIMD of a 256-CU chip, each looping
+                const uint64_t waves = a.queue && chunk_waves > kQueueWaves ? kQueueWaves : chunk_waves;
                 if (delta)
-                    hipLaunchKernelGGL((batch_walk_kernel<kDelta>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_walk_kernel<kDelta>), dim3(wave_grid(waves)), dim3(kThreads), 0, s, a);
                 else
-                    hipLaunchKernelGGL((batch_walk_kernel<kPlain>), dim3(wave_grid(chunk_waves)), dim3(kThreads), 0, s, a);
+                    hipLaunchKernelGGL((batch_walk_kernel<kPlain>), dim3(wave_grid(waves)), dim3(kThreads), 0, s, a);
             }
             break;
         default:

@@ -100,7 +100,9 @@ struct BatchArgs {
     uint32_t *item_list;       // per task: its list, bit 31 set on a list's last task
     uint32_t *item_first;      // per task: first task of its list
     uint32_t t_cap;            // task capacity of the scratch arrays
-    uint32_t chunk;            // tasks per wave in the main pass
+    uint32_t chunk;            // tasks per wave in the main pass (per grab, with a work queue)
+    uint32_t *queue;           // decode walk: counter of the next task to grab (zeroed before the walk),
+                               // or null for the static schedule (wave w takes tasks [w chunk, (w + 1) chunk))
     uint32_t *ibytes;          // per task: data bytes (tasks that are not the last of their list)
     uint64_t *ioff;            // per task: exclusive scan of ibytes
     uint32_t *ivsum;           // per task: sum of stored differences (delta decoding)

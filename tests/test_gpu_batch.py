@@ -133,6 +133,31 @@ def test_batch_edge_sizes(chunk, delta):
     check_batch(lists, starts, seed=5 + chunk, tag="edges chunk=%d" % chunk)
 
 
+SVB_BATCH_QUEUE = 0x100
+
+
+@pytest.mark.parametrize("delta", [False, True])
+@pytest.mark.parametrize("chunk", [1, 2, 4, 8])
+def test_batch_work_queue_schedule(chunk, delta):
+    """The decode walk's work-queue schedule (waves grab chunks of tasks from a device counter):
+    the edge sizes, and 70,000 mostly tiny lists (more tasks than the grid's waves take in one
+    grab each), against the oracle; the queue is refused for encoding."""
+    for kind in (2, 3):
+        with pytest.raises(svb.SvbError):
+            svb.svb_set_batch_chunk(kind, SVB_BATCH_QUEUE | chunk)
+        svb.svb_set_batch_chunk(kind, 4)
+    for kind in (0, 1):
+        svb.svb_set_batch_chunk(kind, SVB_BATCH_QUEUE | chunk)
+    lists, starts = make_lists(EDGE_SIZES, seed=61 + chunk, delta=delta)
+    check_batch(lists, starts, seed=62 + chunk, tag="queue edges chunk=%d" % chunk)
+    rng = np.random.default_rng(63 + chunk)
+    sizes = rng.integers(0, 300, size=70_000)
+    lists, starts = make_lists(sizes, seed=64 + chunk, delta=delta)
+    check_batch(lists, starts, seed=65 + chunk, tag="queue many chunk=%d" % chunk)
+    for kind in (0, 1):
+        svb.svb_set_batch_chunk(kind, 4)
+
+
 @pytest.mark.parametrize("delta", [False, True])
 def test_batch_many_small_lists(delta):
     """70,000 lists (more than 16384 lists and tasks), so the scans take the multi-workgroup path."""
