@@ -893,7 +893,7 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
     server.replay((qo, ids), outstanding=512)
     closed = []
     est_qps = None
-    for depth in (256, 1024, 4096, 16384):
+    for depth in (256, 1024, 4096, 16384, 65536):
         nq = 20_000 if est_qps is None else int(min(4e6, max(20_000, 2.0 * est_qps)))
         _, qo, ids = inputs.poisson_queries_flat(nq, 1.0, lists, seed=94 + depth)
         lat, wall = server.replay((qo, ids), outstanding=depth)
@@ -1133,6 +1133,7 @@ def main():
     ap.add_argument("--no-per-list", action="store_true",
                     help="skip the one-call-per-list baseline of the batched measurement")
     ap.add_argument("--serve-slots", type=int, default=16, help="stream slots of the serving runtime")
+    ap.add_argument("--serve-depth", type=int, default=16384, help="with --only serve: queries outstanding")
     ap.add_argument("--serve-batch-lists", type=int, default=16384, help="most lists per serving batch")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of each open-loop serving window (seconds of arrivals)")
@@ -1170,7 +1171,7 @@ def main():
               "(--gpus %d requested)." % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.only == "serve":
-        profile_serve(args.steps, slots=args.serve_slots, max_batch_lists=args.serve_batch_lists)
+        profile_serve(args.steps, depth=args.serve_depth, slots=args.serve_slots, max_batch_lists=args.serve_batch_lists)
         return
     if args.only:
         profile_only(args.only, args.steps, args.warmup, args.decode_variant, args.dirty_flush)

@@ -33,7 +33,9 @@
 // arriving query: the host passes three numbers per batch instead of a table
 // entry per list.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -662,31 +664,56 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
     typedef std::chrono::steady_clock clock;
     const clock::time_point t0 = clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    // A second host thread sizes the queries as they arrive (their lists'
+    // lengths: result size, segments, and the counts the batch-table kernel
+    // reads), while this one launches and retires batches: queries [0,
+    // released) have arrived, [0, sized) are sized.
+    std::atomic<uint64_t> released{0}, sized{0};
+    std::atomic<bool> stop{false}, too_big{false};
+    std::thread sizer([&] {
+        const uint32_t *cnt = s->counts32.data();  // (prefetching a few queries ahead measured slower)
+        uint64_t q = 0;
+        while (q < nq && !stop.load(std::memory_order_relaxed)) {
+            const uint64_t r = released.load(std::memory_order_acquire);
+            if (q == r) {
+                __builtin_ia32_pause();
+                continue;
+            }
+            for (; q < r; ++q) {
+                uint64_t ints = 0, tasks = 0;
+                for (uint64_t i = qoff[q]; i < qoff[q + 1]; ++i) {
+                    const uint32_t c = cnt[lists[i]];  // 2^32 - 1: at least that long, never admitted
+                    h_cnt[i - qoff[0]] = c;
+                    ints += c;
+                    tasks += (c + kSegInts - 1) / kSegInts;
+                }
+                if (ints > R || ints >= kBatchIntsMax) {
+                    too_big.store(true, std::memory_order_relaxed);
+                    stop.store(true, std::memory_order_relaxed);
+                    break;
+                }
+                qints[q] = ints;
+                qtasks[q] = tasks;
+                if ((q & 255) == 255) sized.store(q + 1, std::memory_order_release);
+            }
+            sized.store(q, std::memory_order_release);
+        }
+    });
     uint64_t next = 0, launched = 0, done = 0;
     while (st == SVB_OK && done < nq) {
-        // arrivals: due (open loop) or room under the outstanding limit (closed
-        // loop); a query's size is looked up as it arrives
+        // arrivals: due (open loop) or room under the outstanding limit (closed loop)
         const double t = now_s();
         const uint64_t was = next;
         while (next < nq && (arrival_s ? arrival_s[next] <= t : next - done < outstanding)) {
-            uint64_t ints = 0, tasks = 0;
-            const uint32_t *cnt = s->counts32.data();  // (prefetching a few queries ahead measured slower)
-            for (uint64_t i = qoff[next]; i < qoff[next + 1]; ++i) {
-                const uint32_t c = cnt[lists[i]];  // 2^32 - 1: at least that long, never admitted
-                h_cnt[i - qoff[0]] = c;
-                ints += c;
-                tasks += (c + kSegInts - 1) / kSegInts;
-            }
-            if (ints > R || ints >= kBatchIntsMax) {
-                st = SVB_ERR_NOMEM;  // can never be admitted
-                break;
-            }
-            qints[next] = ints;
-            qtasks[next] = tasks;
             sent[next] = arrival_s ? arrival_s[next] : t;
             ++next;
         }
-        if (st != SVB_OK) break;
+        if (next != was) released.store(next, std::memory_order_release);
+        if (too_big.load(std::memory_order_relaxed)) {
+            st = SVB_ERR_NOMEM;  // a query that can never be admitted
+            break;
+        }
+        const uint64_t ready = sized.load(std::memory_order_acquire);
         s->stats[3] += next - was;
         // retire: every finished slot is free again at once (batches of
         // different sizes finish out of order); their ring regions are freed
@@ -718,21 +745,21 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
         // launch: the waiting queries in order, as many as a batch and the
         // ring's free region hold, on a free slot
         bool launched_now = false;
-        if (launched < next) {
+        if (launched < ready) {
             Slot *slot = nullptr;
             bool busy = false;
             for (Slot &sl : s->slots) {
                 if (!sl.busy && !slot) slot = &sl;
                 busy |= sl.busy;
             }
-            const uint64_t waiting_lists = qoff[next] - qoff[launched];
+            const uint64_t waiting_lists = qoff[ready] - qoff[launched];
             const bool hold = busy && waiting_lists < s->min_batch_lists &&
                               (t - sent[launched]) * 1e9 < (double)s->max_wait_ns;
             uint64_t pos = 0;
             const uint64_t room = slot && !hold ? ring_space(qints[launched], &pos) : 0;
             if (slot && !hold && room >= qints[launched]) {
                 uint64_t b = launched, ints = 0, tasks = 0;
-                while (b < next && qoff[b + 1] - qoff[launched] <= s->max_batch_lists && ints + qints[b] <= room &&
+                while (b < ready && qoff[b + 1] - qoff[launched] <= s->max_batch_lists && ints + qints[b] <= room &&
                        ints + qints[b] <= kBatchIntsMax) {
                     ints += qints[b];
                     tasks += qtasks[b];
@@ -791,6 +818,8 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
                 }
         }
     }
+    stop.store(true, std::memory_order_relaxed);
+    sizer.join();
     // wait for what is still on the device (after an error), then give the ring back
     for (Batch &b : fifo)
         if (!b.done) {
