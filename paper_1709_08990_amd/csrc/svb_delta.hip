@@ -58,6 +58,9 @@ __device__ __forceinline__ uint32_t sad_chunk(const u32x4a &w, uint32_t acc) {
     return sad_bytes(w.w, acc);
 }
 
+// The low L bytes of a dword, L in 1..4.
+__device__ __forceinline__ uint32_t int_mask(uint32_t L) { return 0xFFFFFFFFu >> (32u - 8u * L); }
+
 // Bytes [0, k) of a dword, k in 0..4.
 __device__ __forceinline__ uint32_t low_bytes_mask(int32_t k) {
     return k <= 0 ? 0u : (k >= 4 ? 0xFFFFFFFFu : ((1u << (8 * k)) - 1u));
@@ -216,6 +219,7 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
     const uint64_t b0 = sl.g * kGroupCtrl + 16ull * lane;
     const uint64_t last_block = nblocks - 1;
     const uint32_t last_r = (uint32_t)(((p.n - 1) & 3) + 1);
+    const bool full_group = (sl.g + 1) * kGroupInts <= p.n;
     // the correction of one block: its first byte at pos (from abase), control byte cb, r integers
     auto block_corr = [&](uint32_t pos, uint32_t cb, uint32_t r) -> uint32_t {
         uint32_t corr = 0;
@@ -226,7 +230,7 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
                 const uint32_t L = ((cb >> (2 * j)) & 3u) + 1u;
                 const uint32_t *src = (const uint32_t *)stage;
                 const uint32_t x = __builtin_amdgcn_alignbyte(src[(q >> 2) + 1], src[q >> 2], q & 3u);
-                const uint32_t v = (j < r) ? (x & low_bytes_mask((int32_t)L)) : 0u;
+                const uint32_t v = (j < r) ? (x & int_mask(L)) : 0u;
                 corr += v - sad_bytes(v, 0u);
                 q += L;
             }
@@ -242,7 +246,7 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
             for (uint32_t j = 0; j < 4; ++j) {
                 const uint32_t L = ((cb >> (2 * j)) & 3u) + 1u;
                 const uint32_t x = __builtin_amdgcn_alignbyte(pick8((q >> 2) + 1, w0, w1), pick8(q >> 2, w0, w1), q & 3u);
-                const uint32_t v = (j < r) ? (x & low_bytes_mask((int32_t)L)) : 0u;
+                const uint32_t v = (j < r) ? (x & int_mask(L)) : 0u;
                 corr += v - sad_bytes(v, 0u);
                 q += L;
             }
@@ -257,7 +261,7 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
         pos = sh16 + off + 4 * b + pick4(i, pre[0], pre[1], pre[2], pre[3]) + __builtin_popcount(low) +
               __builtin_popcount(low & 0xAAAAAAAAu);
         cb = (ci >> (8 * k)) & 0xFFu;
-        r = (b0 + b == last_block) ? last_r : 4u;
+        r = (full_group || b0 + b != last_block) ? 4u : last_r;  // a full group's blocks are all whole
     };
     // the blocks with a non-zero control byte are few on most streams but
     // unevenly spread over the lanes: up to kCorrList of them are listed in

@@ -457,6 +457,7 @@ __device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool full = (s + 1) * kSegInts <= e.n;  // wave-uniform: no integer of the segment lies past n
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         uint32_t pos = sh + off[k];
@@ -464,7 +465,7 @@ __device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64
         for (uint32_t j = 0; j < 4; ++j) {
             const uint32_t code = (sv.c[k] >> (2 * j)) & 3u;
             const uint64_t i = (s * kSegCtrl + kWave * k + lane) * 4 + j;  // integers past n are not written
-            if (i < e.n) {
+            if (full || i < e.n) {
                 const uint32_t val = sv.v[k][j];
                 const uint32_t w = pos >> 2, sb = pos & 3u;
                 atomicOr(stage + w, val << (8u * sb));
@@ -480,16 +481,19 @@ __device__ __forceinline__ uint32_t encode_segment(const EncodeStream &e, uint64
 #pragma unroll
     for (uint32_t i = 0; i < 5; ++i) {
         const uint32_t c = lane + kWave * i;
-        if (c < nch) {
-            const uint32_t lo = 16 * c, hi = lo + 16;
-            if (lo >= sh && hi <= end) {
-                *gptr((u32x4a *)(abase + lo)) = ((const u32x4a *)stage)[c];
-            } else {
-                const uint32_t from = lo > sh ? lo : sh;
-                const uint32_t to = hi < end ? hi : end;
-                for (uint32_t q = from; q < to; ++q) gptr(abase)[q] = (uint8_t)(stage[q >> 2] >> (8u * (q & 3u)));
-            }
-        }
+        const uint32_t lo = 16 * c;
+        if (c < nch && lo >= sh && lo + 16 <= end) *gptr((u32x4a *)(abase + lo)) = ((const u32x4a *)stage)[c];
+    }
+    // the span's first and last chunk, when neighbouring segments own part of
+    // them: one byte per lane (lanes 0-15 the first chunk, 16-31 the last),
+    // only the bytes inside [sh, end)
+    if (lane < 32) {
+        const uint32_t c = lane < 16 ? 0u : nch - 1;
+        const uint32_t q = 16 * c + (lane & 15u);
+        const bool first_edge = sh != 0 || end < 16;  // chunk 0 is partial
+        const bool last_edge = end != 16 * nch;       // chunk nch - 1 is partial (the same chunk when nch = 1)
+        const bool mine = lane < 16 ? first_edge : (last_edge && nch > 1);
+        if (nch && mine && q >= sh && q < end) gptr(abase)[q] = (uint8_t)(stage[q >> 2] >> (8u * (q & 3u)));
     }
     // the next segment clears this area: LDS operations of a wave complete in order
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
