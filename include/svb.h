@@ -32,8 +32,9 @@
  *    are ordered by the stream.
  *  - The only library-owned memory is that scratch workspace (and, for a
  *    serving pool, the server's own buffers): 12 bytes per encoder segment of
- *    1024 integers (byte count, byte offset), 20 bytes per decoder group of
- *    4096 integers (byte total, byte offset, value sum, value prefix), about
+ *    1024 integers (byte count, byte offset), about 13 bytes per decoder
+ *    group of 4096 integers (byte total and value sum per group; byte total,
+ *    value sum, byte offset and value prefix per block of four groups), about
  *    96 bytes per batched segment, plus the scans' partial sums; grown on
  *    demand, freed by svb_release_workspace.
  *  - Return value: SVB_OK (0) or a negative svb_status.  The library never

@@ -147,23 +147,28 @@ int variant_choice(bool delta) {
     return it == g_variant.end() ? -1 : it->second;
 }
 
-// Scratch layout of a decode of n integers: per group data bytes (u32), data
-// offset (u64, or u32 when the stream is under 4 GiB), value sum (u32), value
-// prefix (u32), then the scans' partial sums.
+// Scratch layout of a decode of n integers: per group its data bytes (u32)
+// and value sum (u32), per block of four groups (one workgroup of the passes
+// that take a group per wave) the same two totals, the block's data offset
+// (u32 when the stream is under 4 GiB, else u64) and value prefix (u32), then
+// the scans' partial sums.  Group arrays hold whole blocks.
 struct DecodeLayout {
-    uint64_t groups, o_gbytes, o_goff, o_gvsum, o_gvpre, o_scan, need;
+    uint64_t groups, blocks, o_gbytes, o_bbytes, o_boff, o_gvsum, o_bvsum, o_bvpre, o_scan, need;
 };
 
 DecodeLayout decode_layout(uint64_t n) {
     auto up16 = [](uint64_t b) { return (b + 15) & ~15ull; };
     DecodeLayout L;
     L.groups = (n + kGroupInts - 1) / kGroupInts;
+    L.blocks = (L.groups + 3) / 4;
     L.o_gbytes = 0;
-    L.o_goff = L.o_gbytes + up16(4 * L.groups);
-    L.o_gvsum = L.o_goff + up16(8 * (L.groups + 1));
-    L.o_gvpre = L.o_gvsum + up16(4 * L.groups);
-    L.o_scan = L.o_gvpre + up16(4 * L.groups);
-    L.need = L.o_scan + up16(scan_scratch_bytes(L.groups));
+    L.o_bbytes = L.o_gbytes + up16(16 * L.blocks);
+    L.o_boff = L.o_bbytes + up16(4 * L.blocks);
+    L.o_gvsum = L.o_boff + up16(8 * (L.blocks + 1));
+    L.o_bvsum = L.o_gvsum + up16(16 * L.blocks);
+    L.o_bvpre = L.o_bvsum + up16(4 * L.blocks);
+    L.o_scan = L.o_bvpre + up16(4 * L.blocks);
+    L.need = L.o_scan + up16(scan_scratch_bytes(L.blocks));
     return L;
 }
 
@@ -179,26 +184,21 @@ int decode_launches(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *
     const bool sums_by_decoding = chosen < 0 ? (in_bytes - (n + 3) / 4) / groups > kByteSumsMaxSpan
                                              : (chosen & kVariantSumsByDecoding) != 0;
     int st;
-    // data-stream offset of every group (and segment), from the control stream
+    // data bytes of every group and block of groups, from the control stream
     GroupBytesArgs ga;
     ga.in = in;
     ga.in_bytes = in_bytes;
     ga.n = n;
     ga.groups = groups;
     ga.gbytes = (uint32_t *)(sc + L.o_gbytes);
+    ga.bbytes = (uint32_t *)(sc + L.o_bbytes);
     if ((st = run("group_bytes", [&] { return launch_group_bytes(ga, s); })) != SVB_OK) return st;
-    // offsets below 2^32 (a data stream under 4 GiB) scan in 32 bits: half
-    // the bytes written and read
+    // block offsets below 2^32 (a data stream under 4 GiB) scan in 32 bits
     const bool off32 = in_bytes < (1ull << 32);
-    // the total lands after the last group's offset (the value-sum pass reads
-    // each group's end)
-    void *goff_end = off32 ? (void *)((uint32_t *)(sc + L.o_goff) + groups)
-                           : (void *)((uint64_t *)(sc + L.o_goff) + groups);
     if ((st = run("scan_offsets", [&] {
-             return launch_scan(ga.gbytes, sc + L.o_goff, groups, !off32, 0u, s, goff_end, sc + L.o_scan);
+             return launch_scan(ga.bbytes, sc + L.o_boff, L.blocks, !off32, 0u, s, nullptr, sc + L.o_scan);
          })) != SVB_OK)
         return st;
-    const uint32_t *goff32 = off32 ? (const uint32_t *)(sc + L.o_goff) : nullptr;
 
     DecodeArgs a = {};
     a.in = in;
@@ -207,21 +207,24 @@ int decode_launches(uint64_t n, const uint8_t *in, uint64_t in_bytes, uint32_t *
     a.out = out;
     a.err = err;
     a.groups = groups;
-    a.goff = (const uint64_t *)(sc + L.o_goff);
+    a.gbytes = ga.gbytes;
+    a.boff32 = off32 ? (const uint32_t *)(sc + L.o_boff) : nullptr;
+    a.boff = off32 ? nullptr : (const uint64_t *)(sc + L.o_boff);
     a.gvsum = (uint32_t *)(sc + L.o_gvsum);
-    a.gvpre = (const uint32_t *)(sc + L.o_gvpre);
+    a.bvsum = (uint32_t *)(sc + L.o_bvsum);
+    a.bvpre = (const uint32_t *)(sc + L.o_bvpre);
     if (delta) {
-        // value sum of every group, then start + their exclusive prefix
+        // value sum of every group and block, then start + the blocks' exclusive prefix
         if ((st = run("group_sums", [&] {
-                 return sums_by_decoding ? launch_decode(a, kSums, s, zc, goff32) : launch_group_sums(a, goff32, s);
+                 return sums_by_decoding ? launch_decode(a, kSums, s, zc) : launch_group_sums(a, s);
              })) != SVB_OK)
             return st;
         if ((st = run("scan_sums", [&] {
-                 return launch_scan(a.gvsum, sc + L.o_gvpre, groups, false, start, s, nullptr, sc + L.o_scan);
+                 return launch_scan(a.bvsum, sc + L.o_bvpre, L.blocks, false, start, s, nullptr, sc + L.o_scan);
              })) != SVB_OK)
             return st;
     }
-    return run(delta ? "decode_delta" : "decode", [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc, goff32); });
+    return run(delta ? "decode_delta" : "decode", [&] { return launch_decode(a, delta ? kDelta : kPlain, s, zc); });
 }
 
 // Argument checks shared by the decode entry points: SVB_OK to go on, 1 for

@@ -9,9 +9,10 @@
 //
 //   1. group_bytes_kernel: data bytes of every group (kGroupInts integers),
 //      from the control stream alone: 4 integers per control byte plus the
-//      sum of its codes;
-//   2. a device scan (svb_scan.hip) of the group byte counts -> each group's
-//      offset in the data stream;
+//      sum of its codes, and of every block of four groups;
+//   2. a device scan (svb_scan.hip) of the block byte counts -> each block's
+//      offset in the data stream (a group's is its block's plus the groups
+//      before it in the block);
 //   3. decode_kernel: one wave per group walks its segments (1024 integers =
 //      256 control bytes each) in order.  Plain decoding stores the integers.
 //      Delta decoding first needs each group's sum of stored differences
@@ -36,61 +37,49 @@ namespace svb {
 // --------------------------------------------------------------------------
 // 1. data bytes per group
 
-// kBytesGroups groups per wave, lane l reading control bytes 16 l .. 16 l + 15
-// of each (one 16-byte load and, when the stream is not 4-byte aligned, one
-// more dword): every load of the wave is issued before any is used, so a wave
-// keeps kBytesGroups KiB in flight.  Each control byte stands for 4 integers
-// plus the sum of its codes (Section 4).
-#ifndef SVB_BYTES_GROUPS
-#define SVB_BYTES_GROUPS 1  // measured at 2^28: 1, 2, 4 groups per wave 0.398, 0.401, 0.403 ms per delta call
-#endif
-constexpr uint32_t kBytesGroups = SVB_BYTES_GROUPS;
+// One group per wave, lane l reading control bytes 16 l .. 16 l + 15 of it
+// (one 16-byte load and, when the stream is not 4-byte aligned, one more
+// dword).  Each control byte stands for 4 integers plus the sum of its codes
+// (Section 4).  The workgroup's four waves also write their block's total.
+// (Measured at 2^28: one, two or four groups per wave 0.398, 0.401, 0.403 ms
+// per delta call.)
 static_assert(kGroupCtrl == 16 * kWave, "16 control bytes per lane and group");
 
 __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p) {
+    __shared__ uint32_t s_part[kWaves];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-    const uint64_t g0 = ((uint64_t)blockIdx.x * kWaves + wave) * kBytesGroups;
-    if (g0 >= p.groups) return;
+    const uint64_t g = (uint64_t)blockIdx.x * kWaves + wave;
     const uint64_t full = p.n / kGroupInts;  // groups whose 1024 control bytes all lie below ceil(n/4)
-    uint32_t x[kBytesGroups][4];
-#pragma unroll
-    for (uint32_t k = 0; k < kBytesGroups; ++k) {
-        const uint64_t g = g0 + k;
-        if (g >= full) break;  // wave-uniform
+    uint32_t bytes = 0;
+    if (g < full) {
         const uint8_t *cp = p.in + g * kGroupCtrl + 16ull * lane;
         const uint32_t sh = (uint32_t)((uintptr_t)cp & 3u);
         const uint32_t *ap = (const uint32_t *)(cp - sh);
         const u32x4 w = *gptr((const u32x4 *)ap);
         const uint32_t w4 = sh ? gptr(ap)[4] : 0u;
-        x[k][0] = __builtin_amdgcn_alignbyte(w.y, w.x, sh);
-        x[k][1] = __builtin_amdgcn_alignbyte(w.z, w.y, sh);
-        x[k][2] = __builtin_amdgcn_alignbyte(w.w, w.z, sh);
-        x[k][3] = __builtin_amdgcn_alignbyte(w4, w.w, sh);
-    }
+        const uint32_t x[4] = {__builtin_amdgcn_alignbyte(w.y, w.x, sh), __builtin_amdgcn_alignbyte(w.z, w.y, sh),
+                               __builtin_amdgcn_alignbyte(w.w, w.z, sh), __builtin_amdgcn_alignbyte(w4, w.w, sh)};
+        uint32_t codes = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kBytesGroups; ++k) {
-        const uint64_t g = g0 + k;
-        if (g >= p.groups) break;  // wave-uniform
-        uint32_t bytes;
-        if (g < full) {
-            uint32_t codes = 0;
-#pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) codes += __builtin_popcount(x[k][i]) + __builtin_popcount(x[k][i] & 0xAAAAAAAAu);
-            bytes = 64u + codes;
-        } else {
-            // the stream's last, partial group: byte loads, integers past n not counted
-            const uint64_t nblocks = (p.n + 3) >> 2;
-            const uint32_t last_r = (p.n & 3) ? (uint32_t)(p.n & 3) : 4u;
-            bytes = 0;
-            for (uint32_t i = 0; i < 16; ++i) {
-                const uint64_t b = g * kGroupCtrl + 16ull * lane + i;
-                if (b < nblocks) bytes += control_data_bytes(gptr(p.in)[b], b == nblocks - 1 ? last_r : 4u);
-            }
+        for (uint32_t i = 0; i < 4; ++i) codes += __builtin_popcount(x[i]) + __builtin_popcount(x[i] & 0xAAAAAAAAu);
+        bytes = 64u + codes;
+    } else if (g < p.groups) {
+        // the stream's last, partial group: byte loads, integers past n not counted
+        const uint64_t nblocks = (p.n + 3) >> 2;
+        const uint32_t last_r = (p.n & 3) ? (uint32_t)(p.n & 3) : 4u;
+        for (uint32_t i = 0; i < 16; ++i) {
+            const uint64_t b = g * kGroupCtrl + 16ull * lane + i;
+            if (b < nblocks) bytes += control_data_bytes(gptr(p.in)[b], b == nblocks - 1 ? last_r : 4u);
         }
-        const uint32_t tot = wave_last(wave_incl_scan(bytes));
-        if (lane == 0) p.gbytes[g] = tot;
     }
+    const uint32_t tot = wave_last(wave_incl_scan(bytes));
+    if (lane == 0) {
+        p.gbytes[g] = tot;  // 0 past the last group (the array holds whole blocks)
+        s_part[wave] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) p.bbytes[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
 }
 
 // --------------------------------------------------------------------------
@@ -99,8 +88,9 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 // Group-per-wave decode: wave w of workgroup b decodes group 4 b + w,
 // segment by segment.
 //   kPlain: store the integers.
-//   kDelta: store their running sum (Section 2), continuing from gvpre[group].
-//   kSums:  store nothing; write the group's sum of decoded values to gvsum.
+//   kDelta: store their running sum (Section 2), continuing from the group's carry.
+//   kSums:  store nothing; write the group's sum of decoded values to gvsum,
+//           and the block's to bvsum.
 //   ZC: rows of all-zero control bytes take the widening path of
 //       extract_segment (the zero-control variant).
 // Delta decoding takes the groups last to first: the value-sum pass has just
@@ -122,20 +112,21 @@ __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p)
 #define SVB_DECODE_REVERSE 1
 #endif
 template <int MODE, bool ZC>
-__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const uint32_t *goff32) {
+__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
+    __shared__ uint32_t s_part[kWaves];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const uint64_t gl = (uint64_t)blockIdx.x * kWaves + wave;
-    if (gl >= p.groups) return;
+    if (MODE != kSums && gl >= p.groups) return;  // (the sums mode's waves all reach the block total)
     const uint64_t g = (MODE == kDelta && SVB_DECODE_REVERSE) ? p.groups - 1 - gl : gl;
     uint8_t *stage = s_stage + wave * kStageBytes;
     const uint64_t segs = (p.n + kSegInts - 1) / kSegInts;
     const uint64_t s0 = g * kGroupSegs;
-    const uint64_t s_end = s0 + kGroupSegs < segs ? s0 + kGroupSegs : segs;
-    uint32_t carry = (MODE == kDelta) ? p.gvpre[g] : 0u;
+    const uint64_t s_end = g >= p.groups ? s0 : (s0 + kGroupSegs < segs ? s0 + kGroupSegs : segs);
+    uint32_t carry = (MODE == kDelta) ? group_carry(p, g) : 0u;
     Walker<MODE == kPlain ? SVB_PLAIN_DEPTH : SVB_DELTA_DEPTH> w;
-    walker_begin(p, w, s0, s_end, goff32 ? (uint64_t)goff32[g] : p.goff[g], lane);
+    if (s0 < s_end) walker_begin(p, w, s0, s_end, group_offset(p, g), lane);
     for (uint64_t s = s0; s < s_end; ++s) {
         SegPlan seg;
         uint32_t sh16;
@@ -153,37 +144,43 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p, const ui
             store_segment(p, s, lane, v, 0u);
         }
     }
-    if (w.corrupt && p.err && lane == 0) *p.err = SVB_DECODE_CORRUPT;
-    if (MODE == kSums && lane == 0) p.gvsum[g] = carry;
+    if (s0 < s_end && w.corrupt && p.err && lane == 0) *p.err = SVB_DECODE_CORRUPT;
+    if (MODE == kSums) {
+        if (lane == 0) {
+            p.gvsum[g] = carry;  // 0 past the last group (the array holds whole blocks)
+            s_part[wave] = carry;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) p.bvsum[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    }
 }
 
 // --------------------------------------------------------------------------
 // launchers
 
 hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s) {
-    const uint64_t waves = (a.groups + kBytesGroups - 1) / kBytesGroups;
-    const uint64_t grid = (waves + kWaves - 1) / kWaves;
+    const uint64_t grid = (a.groups + kWaves - 1) / kWaves;
     hipLaunchKernelGGL(group_bytes_kernel, dim3((uint32_t)grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc, const uint32_t *goff32) {
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc) {
     const uint32_t grid = (uint32_t)((a.groups + kWaves - 1) / kWaves);
     if (mode == kPlain) {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kPlain, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kPlain, true>), dim3(grid), dim3(kThreads), 0, s, a);
         else
-            hipLaunchKernelGGL((decode_kernel<kPlain, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kPlain, false>), dim3(grid), dim3(kThreads), 0, s, a);
     } else if (mode == kDelta) {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kDelta, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kDelta, true>), dim3(grid), dim3(kThreads), 0, s, a);
         else
-            hipLaunchKernelGGL((decode_kernel<kDelta, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kDelta, false>), dim3(grid), dim3(kThreads), 0, s, a);
     } else {
         if (zc)
-            hipLaunchKernelGGL((decode_kernel<kSums, true>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kSums, true>), dim3(grid), dim3(kThreads), 0, s, a);
         else
-            hipLaunchKernelGGL((decode_kernel<kSums, false>), dim3(grid), dim3(kThreads), 0, s, a, goff32);
+            hipLaunchKernelGGL((decode_kernel<kSums, false>), dim3(grid), dim3(kThreads), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -316,29 +316,37 @@ __device__ __forceinline__ uint32_t group_sum(const DecodeArgs &p, uint64_t g, u
 #define SVB_SUMS_WPE 8
 #endif
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SVB_SUMS_WPE, 8))) void group_sums_kernel(
-    DecodeArgs p, const uint32_t *goff32) {
+    DecodeArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[kWaves * kSumLds];
+    __shared__ uint32_t s_part[kWaves];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint64_t g = (uint64_t)blockIdx.x * kWaves + wave;
-    if (g >= p.groups) return;
-    const uint64_t data_bytes = p.in_bytes - ((p.n + 3) >> 2);
-    const uint64_t gofs = goff32 ? (uint64_t)goff32[g] : p.goff[g];
-    const uint64_t gend = goff32 ? (uint64_t)goff32[g + 1] : p.goff[g + 1];
     uint32_t sum = 0;
-    if (gend > data_bytes) {
-        if (p.err && lane == 0) *p.err = SVB_DECODE_CORRUPT;
-    } else {
-        sum = group_sum(p, g, gofs, gend, lane, s_lds + wave * kSumLds);
+    if (g < p.groups) {
+        const uint64_t data_bytes = p.in_bytes - ((p.n + 3) >> 2);
+        const uint64_t gofs = group_offset(p, g);
+        const uint64_t gend = gofs + p.gbytes[g];
+        if (gend > data_bytes) {
+            if (p.err && lane == 0) *p.err = SVB_DECODE_CORRUPT;
+        } else {
+            sum = group_sum(p, g, gofs, gend, lane, s_lds + wave * kSumLds);
+        }
     }
-    if (lane == 0) p.gvsum[g] = sum;
+    // the block's total too (waves past the last group count 0)
+    if (lane == 0) {
+        p.gvsum[g] = sum;
+        s_part[wave] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) p.bvsum[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
 }
 
 }  // namespace
 
-hipError_t launch_group_sums(const DecodeArgs &a, const uint32_t *goff32, hipStream_t s) {
+hipError_t launch_group_sums(const DecodeArgs &a, hipStream_t s) {
     const uint32_t grid = (uint32_t)((a.groups + kWaves - 1) / kWaves);
-    hipLaunchKernelGGL(group_sums_kernel, dim3(grid), dim3(kThreads), 0, s, a, goff32);
+    hipLaunchKernelGGL(group_sums_kernel, dim3(grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

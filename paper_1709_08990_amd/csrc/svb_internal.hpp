@@ -22,12 +22,18 @@ constexpr uint64_t kGroupInts = (uint64_t)kSegInts * kGroupSegs;
 constexpr uint64_t kGroupCtrl = kGroupInts / 4;
 static_assert(kGroupSegs >= 4 && kGroupSegs <= 64 && (64 % kGroupSegs) == 0, "group of 4..64 segments");
 
+// Groups come in blocks of kWaves (one workgroup of the passes that take one
+// group per wave): the passes that produce per-group byte counts and value
+// sums also write each block's total, and the scans run over the block
+// totals; a group's offset or carry is its block's prefix plus the at most
+// kWaves - 1 group values before it in the block.
 struct GroupBytesArgs {
     const uint8_t *in;     // stream; its first ceil(n/4) bytes are the control stream
     uint64_t in_bytes;
     uint64_t n;
     uint64_t groups;
-    uint32_t *gbytes;      // out: data bytes of each group
+    uint32_t *gbytes;      // out: data bytes of each group (an array of whole blocks)
+    uint32_t *bbytes;      // out: data bytes of each block of groups
 };
 
 struct DecodeArgs {
@@ -37,9 +43,12 @@ struct DecodeArgs {
     uint32_t *out;
     uint32_t *err;
     uint64_t groups;
-    const uint64_t *goff;  // data-stream byte offset of each group
-    uint32_t *gvsum;       // value sum of each group (written in value-sum mode)
-    const uint32_t *gvpre; // start + exclusive value prefix of each group (read in delta mode)
+    const uint32_t *gbytes;  // data bytes of each group (an array of whole blocks)
+    const uint32_t *boff32;  // data-stream byte offset of each block of groups, 32-bit (a stream under 4 GiB),
+    const uint64_t *boff;    //   else 64-bit
+    uint32_t *gvsum;         // value sum of each group (written by the value-sum pass; whole blocks)
+    uint32_t *bvsum;         // value sum of each block of groups (written by the value-sum pass)
+    const uint32_t *bvpre;   // start + exclusive value prefix of each block (read in delta mode)
 };
 
 // Decoding: mode 0 plain, 1 delta (running sum), 2 value sums per group.
@@ -53,16 +62,12 @@ uint64_t scan_scratch_bytes(uint64_t m);
 hipError_t launch_scan(const uint32_t *in, void *out, uint64_t m, bool wide, uint32_t start, hipStream_t s,
                        void *total = nullptr, void *scratch = nullptr);
 // zc: the zero-control variant (rows of all-zero control bytes widen bytes).
-// goff32 (may be null): 32-bit group offsets, used instead of a.goff (a data
-// stream below 4 GiB).
-hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false,
-                         const uint32_t *goff32 = nullptr);
+hipError_t launch_decode(const DecodeArgs &a, int mode, hipStream_t s, bool zc = false);
 
-// Delta decoding's value sums (gvsum per group) without decoding: the plain sum
-// of each group's data bytes plus a correction per block whose control byte is
-// not zero (svb_delta.hip).  Reads the group offsets and the total after them
-// (goff[groups]).
-hipError_t launch_group_sums(const DecodeArgs &a, const uint32_t *goff32, hipStream_t s);
+// Delta decoding's value sums (gvsum per group, bvsum per block) without
+// decoding: the plain sum of each group's data bytes plus a correction per
+// block whose control byte is not zero (svb_delta.hip).
+hipError_t launch_group_sums(const DecodeArgs &a, hipStream_t s);
 
 // Batched calls.  A task is one 1024-integer segment of one list; each wave of
 // the main pass takes `chunk` consecutive tasks.

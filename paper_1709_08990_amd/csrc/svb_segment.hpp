@@ -11,6 +11,26 @@
 
 namespace svb {
 
+static_assert(kWaves == 4, "a block of groups is one workgroup of four waves, one group each");
+
+// Data-stream byte offset of group g.
+__device__ __forceinline__ uint64_t group_offset(const DecodeArgs &p, uint64_t g) {
+    const uint64_t b = g / 4;
+    uint64_t o = p.boff32 ? (uint64_t)p.boff32[b] : p.boff[b];
+    const uint32_t i = (uint32_t)(g & 3u);
+    const u32x4a x = *(const u32x4a *)(p.gbytes + 4 * b);
+    return o + (i > 0 ? x.x : 0u) + (i > 1 ? x.y : 0u) + (i > 2 ? x.z : 0u);
+}
+
+// Running sum (mod 2^32, from start) before group g.
+__device__ __forceinline__ uint32_t group_carry(const DecodeArgs &p, uint64_t g) {
+    const uint64_t b = g / 4;
+    const uint32_t i = (uint32_t)(g & 3u);
+    const u32x4a x = *(const u32x4a *)(p.gvsum + 4 * b);
+    return p.bvpre[b] + (i > 0 ? x.x : 0u) + (i > 1 ? x.y : 0u) + (i > 2 ? x.z : 0u);
+}
+
+
 // Per-wave LDS staging area.  The segment's data bytes start kStagePad bytes
 // in, so that the 8 aligned bytes read around an integer never fall below the
 // area; 16 x 257 bytes of data (the largest 16-byte-aligned span a segment's
