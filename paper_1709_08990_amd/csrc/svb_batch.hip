@@ -230,13 +230,18 @@ __device__ __forceinline__ void walk_tasks(const BatchArgs &a, uint64_t t0, uint
     }
 }
 
-// The decode walk.  Static schedule: wave w takes tasks [w chunk, (w + 1)
-// chunk).  Work queue (a.queue set): a grid of a few waves per SIMD, each
-// wave grabbing the next `chunk` tasks from a device counter until none are
-// left.  Five waves per SIMD: the delta walk fits 96 registers without
+// The decode walk.  Static schedule (QUEUE false): wave w takes tasks
+// [w chunk, (w + 1) chunk).  Work queue (QUEUE true, a.queue set): a grid of
+// a few waves per SIMD, each wave grabbing the next `chunk` tasks from a
+// device counter until none are left.  The two schedules are separate
+// instantiations so that the static one carries none of the queue loop's
+// registers.  Five waves per SIMD: the delta walk fits 96 registers without
 // spilling, and was measured 12% faster there than at four.
-template <int MODE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_walk_kernel(BatchArgs a) {
+#ifndef SVB_WALK_WPE
+#define SVB_WALK_WPE 5
+#endif
+template <int MODE, bool QUEUE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SVB_WALK_WPE, 8))) void batch_walk_kernel(BatchArgs a) {
     static_assert(MODE == kPlain || MODE == kDelta, "the value sums walk in runs (batch_sums_runs_kernel)");
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     const uint32_t total = task_total(a);
     uint8_t *stage = s_stage + wave * kStageBytes;
     bool corrupt = false;
-    if (a.queue) {
+    if (QUEUE) {
 #pragma unroll 1
         for (;;) {
             uint32_t t0 = 0;
@@ -274,8 +279,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
 // summed.  Writes each task's sum of stored differences to ivsum (0 for the
 // last task of a list, whose sum no carry needs).
 constexpr uint32_t kSumsChunk = 8;  // measured on C4: 8 tasks 175-179 us, 4 186-188, 6 178-180, 16 and 32 slower
-
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_sums_runs_kernel(
+// Seven waves per SIMD (72 registers, no spill): the whole batched C4 call
+// measured 0.648-0.652 ms against 0.668 at five and 0.660 at six; a walker
+// two segments deep (four waves per SIMD, 119 registers) 0.717.
+#ifndef SVB_SUMS_RUN_WPE
+#define SVB_SUMS_RUN_WPE 7
+#endif
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SVB_SUMS_RUN_WPE, 8))) void batch_sums_runs_kernel(
     BatchArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t s_stage[kWaves * kStageBytes];
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -606,10 +616,18 @@ hipError_t launch_batch(const BatchArgs &a, int phase, bool encode, bool delta, 
             } else {
                 // with a work queue: at most five waves per SIMD of a 256-CU chip, each looping
                 const uint64_t waves = a.queue && chunk_waves > kQueueWaves ? kQueueWaves : chunk_waves;
-                if (delta)
-                    hipLaunchKernelGGL((batch_walk_kernel<kDelta>), dim3(wave_grid(waves)), dim3(kThreads), 0, s, a);
-                else
-                    hipLaunchKernelGGL((batch_walk_kernel<kPlain>), dim3(wave_grid(waves)), dim3(kThreads), 0, s, a);
+                const dim3 grid(wave_grid(waves));
+                if (delta) {
+                    if (a.queue)
+                        hipLaunchKernelGGL((batch_walk_kernel<kDelta, true>), grid, dim3(kThreads), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((batch_walk_kernel<kDelta, false>), grid, dim3(kThreads), 0, s, a);
+                } else {
+                    if (a.queue)
+                        hipLaunchKernelGGL((batch_walk_kernel<kPlain, true>), grid, dim3(kThreads), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((batch_walk_kernel<kPlain, false>), grid, dim3(kThreads), 0, s, a);
+                }
             }
             break;
         default:
