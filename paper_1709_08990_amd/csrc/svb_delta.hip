@@ -85,6 +85,17 @@ __device__ __forceinline__ u32x4a load_chunk(const uint8_t *cp, const uint8_t *l
     return w;
 }
 
+// Group g's byte offset in the data stream, and its data bytes, from one load
+// of its block's byte counts.
+__device__ __forceinline__ uint64_t group_span(const DecodeArgs &p, uint64_t g, uint32_t &bytes) {
+    const uint64_t b = g / 4;
+    const uint64_t o = p.boff32 ? (uint64_t)p.boff32[b] : p.boff[b];
+    const uint32_t i = (uint32_t)(g & 3u);
+    const u32x4a x = *(const u32x4a *)(p.gbytes + 4 * b);
+    bytes = pick4(i, x.x, x.y, x.z, x.w);
+    return o + (i > 0 ? x.x : 0u) + (i > 1 ? x.y : 0u) + (i > 2 ? x.z : 0u);
+}
+
 // A group's value sum in two halves, so that its loads can be in flight
 // while the wave does something else: group_sum_issue requests the control
 // bytes and the data span into registers, group_sum_finish stages the span in
@@ -95,7 +106,10 @@ __device__ __forceinline__ u32x4a load_chunk(const uint8_t *cp, const uint8_t *l
 struct SumLoads {
     uint64_t g, gofs;
     uint32_t total, sh16, nch;
-    uint32_t c[4];  // the lane's 16 control bytes (blocks 16 l .. 16 l + 15)
+    u32x4a cw;      // full group: the aligned dwords around the lane's 16 control bytes
+    uint32_t cw4;   //   (a fifth dword when they are not 4-byte aligned)
+    uint32_t csh;   //   and their byte alignment
+    uint32_t c[4];  // the stream's last group: the lane's 16 control bytes (blocks 16 l .. 16 l + 15)
     uint32_t ints;  // integers of those blocks
     u32x4a w[5];    // chunks lane, lane + 64, ... of the span's first 288 chunks
 };
@@ -119,17 +133,19 @@ __device__ __forceinline__ void group_sum_issue(const DecodeArgs &p, uint64_t g,
         const uint8_t *cp = p.in + b0;
         const uint32_t sh = (uint32_t)((uintptr_t)cp & 3u);
         const uint32_t *ap = (const uint32_t *)(cp - sh);
-        const u32x4 w = *gptr((const u32x4 *)ap);
-        const uint32_t w4 = sh ? gptr(ap)[4] : 0u;
-        sl.c[0] = __builtin_amdgcn_alignbyte(w.y, w.x, sh);
-        sl.c[1] = __builtin_amdgcn_alignbyte(w.z, w.y, sh);
-        sl.c[2] = __builtin_amdgcn_alignbyte(w.w, w.z, sh);
-        sl.c[3] = __builtin_amdgcn_alignbyte(w4, w.w, sh);
+        // (aligned in group_sum_finish, so that the span's loads below are
+        // issued before anything waits for these)
+        sl.cw = *gptr((const u32x4a *)ap);
+        sl.cw4 = sh ? gptr(ap)[4] : 0u;
+        sl.csh = sh;
         sl.ints = 64;
     } else {
         // the stream's last group: blocks past the end read as 0, and the
         // codes of integers past n in the last block are cleared
         const uint32_t last_r = (uint32_t)(p.n & 3);
+        sl.cw = u32x4a{0u, 0u, 0u, 0u};
+        sl.cw4 = 0u;
+        sl.csh = 0u;
 #pragma unroll
         for (uint32_t i = 0; i < 4; ++i) sl.c[i] = 0u;
 #pragma unroll
@@ -178,50 +194,64 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
         acc = sad_chunk(inside ? *gptr((const u32x4a *)cp) : load_chunk(cp, lo, hi), acc);
     }
     const uint32_t staged = 16 * (nch < kSpanStage / 16 ? nch : kSpanStage / 16);
-    if (lane < 2) {
-        // lane 0: bytes [0, sh16) of the first chunk; lane 1: the last
-        // chunk's bytes from the span's end on
-        const uint32_t ch = lane ? nch - 1 : 0u;
-        const int32_t xlo = lane ? (int32_t)(sh16 + total - 16 * (nch - 1)) : 0;
-        const int32_t xhi = lane ? 16 : (int32_t)sh16;
-        if (xlo < xhi) {
-            const u32x4a w = load_chunk(abase + 16 * ch, lo, hi);
-            const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
-            uint32_t x = 0;
-#pragma unroll
-            for (int32_t i = 0; i < 4; ++i)
-                x = sad_bytes(wd[i] & low_bytes_mask(xhi - 4 * i) & ~low_bytes_mask(xlo - 4 * i), x);
-            acc -= x;
-        }
-    }
 
-    // the lane's blocks: byte offsets, and which control bytes are not zero
-    uint32_t codes = 0, nzm = 0, pre[4];
+    // the lane's control bytes; per word, the codes before it and the top bit
+    // of each of its non-zero bytes (a block that needs a correction)
+    const bool full_group = (sl.g + 1) * kGroupInts <= p.n;
+    uint32_t c[4];
+    if (full_group) {
+        c[0] = __builtin_amdgcn_alignbyte(sl.cw.y, sl.cw.x, sl.csh);
+        c[1] = __builtin_amdgcn_alignbyte(sl.cw.z, sl.cw.y, sl.csh);
+        c[2] = __builtin_amdgcn_alignbyte(sl.cw.w, sl.cw.z, sl.csh);
+        c[3] = __builtin_amdgcn_alignbyte(sl.cw4, sl.cw.w, sl.csh);
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) c[i] = sl.c[i];
+    }
+    uint32_t codes = 0, nzc = 0, pre[4], nz[4];
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i) {
         pre[i] = codes;
-        codes += __builtin_popcount(sl.c[i]) + __builtin_popcount(sl.c[i] & 0xAAAAAAAAu);
-        const uint32_t y = (((sl.c[i] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | sl.c[i]) & 0x80808080u;  // top bit of each non-zero byte
-        nzm |= ((((y >> 7) * 0x00204081u) >> 21) & 0xFu) << (4 * i);  // ... gathered into a nibble
+        codes += __builtin_popcount(c[i]) + __builtin_popcount(c[i] & 0xAAAAAAAAu);
+        nz[i] = (((c[i] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | c[i]) & 0x80808080u;
+        nzc += __builtin_popcount(nz[i]);
     }
+    // one scan for both the lane's byte offset in the span and its first
+    // slot in the correction list (a group's data bytes, at most 16,384, and
+    // its blocks, 1024, each fit 16 bits)
     const uint32_t bytes = sl.ints + codes;
-    const uint32_t off = wave_incl_scan(bytes) - bytes;
+    const uint32_t both = wave_incl_scan(bytes | (nzc << 16));
+    const uint32_t off = (both & 0xFFFFu) - bytes;
+    const uint32_t nzi = both >> 16;
+    const uint32_t nz_total = wave_last(nzi);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // the span's edges: lane 0 takes back bytes [0, sh16) of the first chunk,
+    // lane 1 the bytes of the last chunk from the span's end on (its chunk sum
+    // minus its first e bytes), both read from the staged copy when it holds
+    // them
+    if (lane < 2) {
+        const uint32_t ch = lane ? nch - 1 : 0u;
+        const int32_t k = lane ? (int32_t)(sh16 + total - 16 * (nch - 1)) : (int32_t)sh16;
+        const u32x4a w = 16 * ch + 16 <= staged ? *(const u32x4a *)(stage + 16 * ch) : load_chunk(abase + 16 * ch, lo, hi);
+        const uint32_t pfx = sad_bytes(w.x & low_bytes_mask(k), 0u) + sad_bytes(w.y & low_bytes_mask(k - 4), 0u) +
+                             sad_bytes(w.z & low_bytes_mask(k - 8), 0u) + sad_bytes(w.w & low_bytes_mask(k - 12), 0u);
+        acc -= lane ? sad_chunk(w, 0u) - pfx : pfx;
+    }
 
     // corrections: each block with a non-zero control byte, read from the
     // staged span (an integer's 4-byte read starts at most 12 bytes into its
     // block and reads 8 aligned bytes, so a block whose first byte lies 24
     // bytes or more before the staged part's end reads only staged bytes;
     // bytes past the span never reach a value, masked to the integer's
-    // length), or else from its two aligned chunks in memory
-    const uint64_t b0 = sl.g * kGroupCtrl + 16ull * lane;
-    const uint64_t last_block = nblocks - 1;
-    const uint32_t last_r = (uint32_t)(((p.n - 1) & 3) + 1);
-    const bool full_group = (sl.g + 1) * kGroupInts <= p.n;
-    // the correction of one block: its first byte at pos (from abase), control byte cb, r integers
-    auto block_corr = [&](uint32_t pos, uint32_t cb, uint32_t r) -> uint32_t {
+    // length), or else from its two aligned chunks in memory.  Every block is
+    // taken as four integers: in the stream's last block the codes of the
+    // integers past n were cleared above, and a one-byte integer needs no
+    // correction (its value is its byte sum).
+    // the correction of one block: its first byte at pos (from abase), control byte cb
+    auto block_corr = [&](uint32_t pos, uint32_t cb) -> uint32_t {
         uint32_t corr = 0;
         if (pos + 24 <= staged) {
             uint32_t q = pos;
@@ -230,14 +260,14 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
                 const uint32_t L = ((cb >> (2 * j)) & 3u) + 1u;
                 const uint32_t *src = (const uint32_t *)stage;
                 const uint32_t x = __builtin_amdgcn_alignbyte(src[(q >> 2) + 1], src[q >> 2], q & 3u);
-                const uint32_t v = (j < r) ? (x & int_mask(L)) : 0u;
+                const uint32_t v = x & int_mask(L);
                 corr += v - sad_bytes(v, 0u);
                 q += L;
             }
         } else {
             // past the staged part: the two aligned chunks around the block, in registers
             const uint32_t o = pos & 15u;
-            const uint32_t C = r + __builtin_popcount(cb) + __builtin_popcount(cb & 0xAAu);
+            const uint32_t C = 4u + __builtin_popcount(cb) + __builtin_popcount(cb & 0xAAu);
             const uint8_t *cp = abase + (pos - o);
             const u32x4a w0 = load_chunk(cp, lo, hi);
             const u32x4a w1 = (o + C > 16) ? load_chunk(cp + 16, lo, hi) : u32x4a{0u, 0u, 0u, 0u};
@@ -246,56 +276,49 @@ __device__ __forceinline__ uint32_t group_sum_finish(const DecodeArgs &p, const 
             for (uint32_t j = 0; j < 4; ++j) {
                 const uint32_t L = ((cb >> (2 * j)) & 3u) + 1u;
                 const uint32_t x = __builtin_amdgcn_alignbyte(pick8((q >> 2) + 1, w0, w1), pick8(q >> 2, w0, w1), q & 3u);
-                const uint32_t v = (j < r) ? (x & int_mask(L)) : 0u;
+                const uint32_t v = x & int_mask(L);
                 corr += v - sad_bytes(v, 0u);
                 q += L;
             }
         }
         return corr;
     };
-    // where block b of the lane (0..15) starts, its control byte and integer count
-    auto block_at = [&](uint32_t b, uint32_t &pos, uint32_t &cb, uint32_t &r) {
-        const uint32_t i = b >> 2, k = b & 3u;
-        const uint32_t ci = pick4(i, sl.c[0], sl.c[1], sl.c[2], sl.c[3]);
-        const uint32_t low = ci & low_bytes_mask((int32_t)k);
-        pos = sh16 + off + 4 * b + pick4(i, pre[0], pre[1], pre[2], pre[3]) + __builtin_popcount(low) +
-              __builtin_popcount(low & 0xAAAAAAAAu);
-        cb = (ci >> (8 * k)) & 0xFFu;
-        r = (full_group || b0 + b != last_block) ? 4u : last_r;  // a full group's blocks are all whole
+    // Every block of the lane with a non-zero control byte, word by word
+    // (so that each word's control bytes and code count are known without
+    // selecting among registers): f(pos, cb) with its first byte at pos (from
+    // abase) and its control byte.
+    auto each_block = [&](auto f) {
+        const uint32_t base = sh16 + off;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            uint32_t y = nz[i];
+            while (y) {
+                const uint32_t sft = (uint32_t)__builtin_ctz(y) - 7u;  // 8 k for byte k of the word
+                y &= y - 1u;
+                const uint32_t low = c[i] & ((1u << sft) - 1u);
+                const uint32_t pos = base + 16u * i + pre[i] + (sft >> 1) + __builtin_popcount(low) +
+                                     __builtin_popcount(low & 0xAAAAAAAAu);
+                f(pos, __builtin_amdgcn_ubfe(c[i], sft, 8));
+            }
+        }
     };
     // the blocks with a non-zero control byte are few on most streams but
     // unevenly spread over the lanes: up to kCorrList of them are listed in
     // LDS and taken one per lane; more are taken by their own lanes
-    const uint32_t nzc = __builtin_popcount(nzm);
-    const uint32_t nzi = wave_incl_scan(nzc);
-    const uint32_t nz_total = wave_last(nzi);
     uint32_t corr = 0;
-    uint32_t m = nzm;
     if (nz_total <= kCorrList) {
         uint32_t *list = (uint32_t *)(stage + kSpanStage);
         uint32_t slot = nzi - nzc;
-        while (m) {
-            const uint32_t b = __builtin_ctz(m);
-            m &= m - 1u;
-            uint32_t pos, cb, r;
-            block_at(b, pos, cb, r);
-            list[slot++] = pos | (cb << 20) | ((r - 1u) << 28);
-        }
+        each_block([&](uint32_t pos, uint32_t cb) { list[slot++] = pos | (cb << 20); });
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane < nz_total) {
             const uint32_t e = list[lane];
-            corr = block_corr(e & 0xFFFFFu, (e >> 20) & 0xFFu, (e >> 28) + 1u);
+            corr = block_corr(e & 0xFFFFFu, e >> 20);
         }
     } else {
-        while (m) {
-            const uint32_t b = __builtin_ctz(m);
-            m &= m - 1u;
-            uint32_t pos, cb, r;
-            block_at(b, pos, cb, r);
-            corr += block_corr(pos, cb, r);
-        }
+        each_block([&](uint32_t pos, uint32_t cb) { corr += block_corr(pos, cb); });
     }
     // the next use of the area overwrites it: LDS operations of a wave complete in order
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -325,8 +348,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(SVB_SU
     uint32_t sum = 0;
     if (g < p.groups) {
         const uint64_t data_bytes = p.in_bytes - ((p.n + 3) >> 2);
-        const uint64_t gofs = group_offset(p, g);
-        const uint64_t gend = gofs + p.gbytes[g];
+        uint32_t gbytes;
+        const uint64_t gofs = group_span(p, g, gbytes);
+        const uint64_t gend = gofs + gbytes;
         if (gend > data_bytes) {
             if (p.err && lane == 0) *p.err = SVB_DECODE_CORRUPT;
         } else {
