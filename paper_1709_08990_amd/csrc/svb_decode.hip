@@ -9,7 +9,7 @@
 //
 //   1. group_bytes_kernel: data bytes of every group (kGroupInts integers),
 //      from the control stream alone: 4 integers per control byte plus the
-//      sum of its codes, and of every block of four groups;
+//      sum of its codes, and of every block of four groups (one per wave);
 //   2. a device scan (svb_scan.hip) of the block byte counts -> each block's
 //      offset in the data stream (a group's is its block's plus the groups
 //      before it in the block);
@@ -37,49 +37,69 @@ namespace svb {
 // --------------------------------------------------------------------------
 // 1. data bytes per group
 
-// One group per wave, lane l reading control bytes 16 l .. 16 l + 15 of it
-// (one 16-byte load and, when the stream is not 4-byte aligned, one more
-// dword).  Each control byte stands for 4 integers plus the sum of its codes
-// (Section 4).  The workgroup's four waves also write their block's total.
-// (Measured at 2^28: one, two or four groups per wave 0.398, 0.401, 0.403 ms
-// per delta call.)
+// One block of four groups per wave: lane l reads control bytes 16 l ..
+// 16 l + 15 of each of the four groups (four 16-byte loads in flight, and one
+// more dword each when the stream is not 4-byte aligned).  Each control byte
+// stands for 4 integers plus the sum of its codes (Section 4).  A group's
+// data bytes are at most 16,384, so two groups share one wave sum; lane 0
+// writes the four group totals and the block's.  (Measured at 2^28 against
+// one group per wave: delta decode 0.3059 -> 0.3045 ms per call, plain
+// decode 0.3077 -> 0.3065.)
 static_assert(kGroupCtrl == 16 * kWave, "16 control bytes per lane and group");
 
 __global__ __launch_bounds__(kThreads) void group_bytes_kernel(GroupBytesArgs p) {
-    __shared__ uint32_t s_part[kWaves];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-    const uint64_t g = (uint64_t)blockIdx.x * kWaves + wave;
+    const uint64_t blk = (uint64_t)blockIdx.x * kWaves + wave;
+    const uint64_t blocks = (p.groups + kWaves - 1) / kWaves;
+    if (blk >= blocks) return;
     const uint64_t full = p.n / kGroupInts;  // groups whose 1024 control bytes all lie below ceil(n/4)
-    uint32_t bytes = 0;
-    if (g < full) {
-        const uint8_t *cp = p.in + g * kGroupCtrl + 16ull * lane;
+    const uint64_t g0 = blk * kWaves;
+    uint32_t bytes[kWaves];
+    if (g0 + kWaves <= full) {
+        const uint8_t *cp = p.in + g0 * kGroupCtrl + 16ull * lane;
         const uint32_t sh = (uint32_t)((uintptr_t)cp & 3u);
         const uint32_t *ap = (const uint32_t *)(cp - sh);
-        const u32x4 w = *gptr((const u32x4 *)ap);
-        const uint32_t w4 = sh ? gptr(ap)[4] : 0u;
-        const uint32_t x[4] = {__builtin_amdgcn_alignbyte(w.y, w.x, sh), __builtin_amdgcn_alignbyte(w.z, w.y, sh),
-                               __builtin_amdgcn_alignbyte(w.w, w.z, sh), __builtin_amdgcn_alignbyte(w4, w.w, sh)};
-        uint32_t codes = 0;
+        u32x4 w[kWaves];
+        uint32_t w4[kWaves];
 #pragma unroll
-        for (uint32_t i = 0; i < 4; ++i) codes += __builtin_popcount(x[i]) + __builtin_popcount(x[i] & 0xAAAAAAAAu);
-        bytes = 64u + codes;
-    } else if (g < p.groups) {
-        // the stream's last, partial group: byte loads, integers past n not counted
+        for (uint32_t j = 0; j < kWaves; ++j) w[j] = *gptr((const u32x4 *)(ap + j * (kGroupCtrl / 4)));
+#pragma unroll
+        for (uint32_t j = 0; j < kWaves; ++j) w4[j] = sh ? gptr(ap + j * (kGroupCtrl / 4))[4] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kWaves; ++j) {
+            const uint32_t x[4] = {__builtin_amdgcn_alignbyte(w[j].y, w[j].x, sh),
+                                   __builtin_amdgcn_alignbyte(w[j].z, w[j].y, sh),
+                                   __builtin_amdgcn_alignbyte(w[j].w, w[j].z, sh),
+                                   __builtin_amdgcn_alignbyte(w4[j], w[j].w, sh)};
+            uint32_t codes = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) codes += __builtin_popcount(x[i]) + __builtin_popcount(x[i] & 0xAAAAAAAAu);
+            bytes[j] = 64u + codes;
+        }
+    } else {
+        // the block of the stream's last, partial group: byte loads, integers
+        // past n not counted, groups past the last 0
         const uint64_t nblocks = (p.n + 3) >> 2;
         const uint32_t last_r = (p.n & 3) ? (uint32_t)(p.n & 3) : 4u;
-        for (uint32_t i = 0; i < 16; ++i) {
-            const uint64_t b = g * kGroupCtrl + 16ull * lane + i;
-            if (b < nblocks) bytes += control_data_bytes(gptr(p.in)[b], b == nblocks - 1 ? last_r : 4u);
+#pragma unroll
+        for (uint32_t j = 0; j < kWaves; ++j) {
+            bytes[j] = 0;
+            const uint64_t g = g0 + j;
+            if (g >= p.groups) continue;
+            for (uint32_t i = 0; i < 16; ++i) {
+                const uint64_t b = g * kGroupCtrl + 16ull * lane + i;
+                if (b < nblocks) bytes[j] += control_data_bytes(gptr(p.in)[b], b == nblocks - 1 ? last_r : 4u);
+            }
         }
     }
-    const uint32_t tot = wave_last(wave_incl_scan(bytes));
+    const uint32_t s01 = wave_last(wave_incl_scan(bytes[0] | (bytes[1] << 16)));
+    const uint32_t s23 = wave_last(wave_incl_scan(bytes[2] | (bytes[3] << 16)));
     if (lane == 0) {
-        p.gbytes[g] = tot;  // 0 past the last group (the array holds whole blocks)
-        s_part[wave] = tot;
+        const u32x4 t = u32x4{s01 & 0xFFFFu, s01 >> 16, s23 & 0xFFFFu, s23 >> 16};
+        *(u32x4 *)(p.gbytes + g0) = t;  // 0 past the last group (the array holds whole blocks)
+        p.bbytes[blk] = t.x + t.y + t.z + t.w;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) p.bbytes[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
 }
 
 // --------------------------------------------------------------------------
@@ -159,8 +179,8 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs p) {
 // launchers
 
 hipError_t launch_group_bytes(const GroupBytesArgs &a, hipStream_t s) {
-    const uint64_t grid = (a.groups + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(group_bytes_kernel, dim3((uint32_t)grid), dim3(kThreads), 0, s, a);
+    const uint64_t blocks = (a.groups + kWaves - 1) / kWaves;  // one per wave
+    hipLaunchKernelGGL(group_bytes_kernel, dim3((uint32_t)((blocks + kWaves - 1) / kWaves)), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
