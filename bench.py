@@ -40,7 +40,8 @@ Prints one JSON line.  Besides the headline it carries:
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it (windows of
-                --serve-seconds, 30 s by default), p50/p99 latency and
+                --serve-seconds, 30 s by default, at most 4e8 queries),
+                p50/p99 latency and
                 integers/s, against the 2^28 single-array rate and against
                 the pool's integers decoded as one array.
 
@@ -835,6 +836,9 @@ def latency_summary(lat, ints, wall):
             "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean())}
 
 
+SERVE_OPEN_MAX_QUERIES = 400_000_000
+
+
 def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
                     arena_bytes=1 << 30, slots=16, max_batch_lists=16384):
     """Serving loop over a device-resident pool of delta-coded posting lists: closed-loop saturation,
@@ -908,8 +912,14 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
     warmup = 0.25  # seconds of arrivals replayed first and left out of the figures (GPU clocks ramp up)
     for load in (0.5, 0.8):
         rate = load * sat["qps"]
-        nq = max(1000, int(rate * (seconds + warmup)))
+        # the replay holds the whole trace (host arrays, list ids on the device, their lengths in
+        # pinned memory): at most SERVE_OPEN_MAX_QUERIES queries, so a high saturation rate
+        # shortens the window below `seconds`
+        nq = min(SERVE_OPEN_MAX_QUERIES, max(1000, int(rate * (seconds + warmup))))
+        log("serving open loop %.1fx: generating %d Poisson arrivals at %.3g queries/s (%.1f s)"
+            % (load, nq, rate, nq / rate))
         times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=97 + int(10 * load))
+        log("serving open loop %.1fx: replaying" % load)
         lat, wall = server.replay((qo, ids), arrivals=times)
         keep = times >= warmup
         ints = query_ints(qo, ids)
