@@ -40,8 +40,8 @@ Prints one JSON line.  Besides the headline it carries:
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it (windows of
-                --serve-seconds, 30 s by default, at most 4e8 queries),
-                p50/p99 latency and
+                --serve-seconds, 30 s by default, replayed in chunks of at
+                most 4e8 queries), p50/p99 latency and
                 integers/s, against the 2^28 single-array rate and against
                 the pool's integers decoded as one array.
 
@@ -912,22 +912,39 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
     warmup = 0.25  # seconds of arrivals replayed first and left out of the figures (GPU clocks ramp up)
     for load in (0.5, 0.8):
         rate = load * sat["qps"]
-        # the replay holds the whole trace (host arrays, list ids on the device, their lengths in
-        # pinned memory): at most SERVE_OPEN_MAX_QUERIES queries, so a high saturation rate
-        # shortens the window below `seconds`
-        nq = min(SERVE_OPEN_MAX_QUERIES, max(1000, int(rate * (seconds + warmup))))
-        log("serving open loop %.1fx: generating %d Poisson arrivals at %.3g queries/s (%.1f s)"
-            % (load, nq, rate, nq / rate))
-        times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=97 + int(10 * load))
-        log("serving open loop %.1fx: replaying" % load)
-        lat, wall = server.replay((qo, ids), arrivals=times)
-        keep = times >= warmup
-        ints = query_ints(qo, ids)
-        r = latency_summary(lat[keep], ints[keep].sum(), wall - warmup)
-        r.update({"load": load, "offered_qps": rate, "window_s": float(times[-1] - warmup), "warmup_s": warmup})
+        # The replay holds a whole trace (host arrays, list ids on the device, their lengths in
+        # pinned memory), so the window is taken in chunks of at most SERVE_OPEN_MAX_QUERIES
+        # queries, each replayed from an idle server with its first `warmup` seconds left out;
+        # the figures are over all chunks (percentiles over every stride-th latency).
+        chunk_s = max(1.0, SERVE_OPEN_MAX_QUERIES / rate - warmup)
+        n_chunks = max(1, int(np.ceil(seconds / chunk_s)))
+        win = seconds / n_chunks
+        stride = max(1, int(rate * seconds) // 50_000_000)
+        sample, n_meas, ints_meas, lat_sum, wall_meas, window = [], 0, 0.0, 0.0, 0.0, 0.0
+        for c in range(n_chunks):
+            nq = max(1000, int(rate * (win + warmup)))
+            log("serving open loop %.1fx: chunk %d/%d, %d Poisson arrivals at %.3g queries/s"
+                % (load, c + 1, n_chunks, nq, rate))
+            times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=97 + int(10 * load) + 1000 * c,
+                                                         distinct=False)
+            lat, wall = server.replay((qo, ids), arrivals=times)
+            keep = times >= warmup
+            kept = lat[keep]
+            n_meas += kept.size
+            ints_meas += float(query_ints(qo.view(np.int64), ids)[keep].sum())
+            lat_sum += float(kept.sum())
+            wall_meas += wall - warmup
+            window += float(times[-1] - warmup)
+            sample.append(kept[::stride].copy())
+            del times, qo, ids, lat, keep, kept
+        sample = np.concatenate(sample)
+        r = {"queries": n_meas, "wall_s": wall_meas, "qps": n_meas / wall_meas, "uint32_per_s": ints_meas / wall_meas,
+             "p50_ms": 1e3 * float(np.percentile(sample, 50)), "p99_ms": 1e3 * float(np.percentile(sample, 99)),
+             "mean_ms": 1e3 * lat_sum / max(1, n_meas), "latency_sample_stride": stride, "chunks": n_chunks,
+             "load": load, "offered_qps": rate, "window_s": window, "warmup_s": warmup}
         opened.append(r)
-        log("serving open loop %.1fx: offered %.0f q/s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
-            % (load, rate, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+        log("serving open loop %.1fx: offered %.0f q/s over %.1f s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
+            % (load, rate, window, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
     st = server.stats()
     server.close()
     assert st["err"] == 0, "a served batch reported corrupt input"

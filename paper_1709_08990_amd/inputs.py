@@ -187,15 +187,20 @@ def poisson_queries(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8):
     return t, [ids[qoff[i]:qoff[i + 1]] for i in range(n_queries)]
 
 
-def poisson_queries_flat(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8):
-    """``poisson_queries`` with the picks flattened: (times, qoff int64[n+1], ids int64)."""
+def poisson_queries_flat(n_queries, qps, n_lists, seed=6, kmin=2, kmax=8, distinct=True):
+    """``poisson_queries`` with the picks flattened: (times, qoff int64[n+1], ids int64).  With
+    ``distinct`` False a query's lists are drawn with replacement (no redraw of repeated ids), and
+    qoff and ids come as uint64 and uint32, the layout the replay reads: for traces of hundreds of
+    millions of queries."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / qps, size=n_queries))
-    ks = rng.integers(kmin, kmax + 1, size=n_queries)
+    ks = rng.integers(kmin, kmax + 1, size=n_queries, dtype=np.int64 if distinct else np.uint8)
     if n_lists < kmax:
         ks = np.minimum(ks, n_lists)
-    qoff = np.zeros(n_queries + 1, dtype=np.int64)
+    qoff = np.zeros(n_queries + 1, dtype=np.int64 if distinct else np.uint64)
     np.cumsum(ks, out=qoff[1:])
+    if not distinct:
+        return t, qoff, rng.integers(0, n_lists, size=int(qoff[-1]), dtype=np.uint32)
     ids = rng.integers(0, n_lists, size=int(qoff[-1]), dtype=np.int64)
     # a query holding a repeated id is drawn again without replacement (queries of equal k are
     # checked together, each id against the ones before it)
