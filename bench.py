@@ -40,8 +40,8 @@ Prints one JSON line.  Besides the headline it carries:
   serving       a pool of 10^6 delta-coded lists (about 1.6e9 integers) kept
                 in HBM, queries of 2..8 lists: closed-loop saturation rate,
                 then Poisson arrivals at 0.5x and 0.8x of it (windows of
-                --serve-seconds, 30 s by default, replayed in chunks of at
-                most 4e8 queries), p50/p99 latency and
+                --serve-seconds, 30 s by default, arrivals drawn in the
+                replay), p50/p99 latency and
                 integers/s, against the 2^28 single-array rate and against
                 the pool's integers decoded as one array.
 
@@ -836,15 +836,16 @@ def latency_summary(lat, ints, wall):
             "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean())}
 
 
-SERVE_OPEN_MAX_QUERIES = 400_000_000
+SERVE_TRACE_QUERIES = 1 << 22  # queries of the open loops' trace, used cyclically
+OPEN_LOOP_BATCHING = (4096, 50)  # lists, microseconds
 
 
 def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
                     arena_bytes=1 << 30, slots=16, max_batch_lists=16384):
     """Serving loop over a device-resident pool of delta-coded posting lists: closed-loop saturation,
-    then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate, then the highest probed
-    Poisson rate an open loop sustains and 0.5x / 0.8x of that; each query 2..8 lists chosen
-    uniformly; latency from arrival to the host seeing the batch complete."""
+    then open-loop Poisson arrivals at 0.5x and 0.8x of the saturation rate for `seconds` each
+    (arrivals drawn in the native replay); each query 2..8 lists chosen uniformly (with replacement
+    in the open loops); latency from arrival to the host seeing the batch complete."""
     from paper_1709_08990_amd import serve
     t0 = time.perf_counter()
     pool = build_pool(svb, torch, np, inputs, lists, total, cap, seed=91)
@@ -910,41 +911,26 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
     sat = max(closed, key=lambda r: r["qps"])
     opened = []
     warmup = 0.25  # seconds of arrivals replayed first and left out of the figures (GPU clocks ramp up)
+    # open loop: Poisson arrivals drawn in the replay itself over a trace of SERVE_TRACE_QUERIES
+    # queries used cyclically, so a window of any length needs no host trace
+    _, bq, bi = inputs.poisson_queries_flat(SERVE_TRACE_QUERIES, 1.0, lists, seed=97, distinct=False)
+    # batches held to 4096 lists or 50 us while another is on the device: the policy that kept the
+    # tail lowest in a sweep of open loops (1024 / 20 us, 4096 / 50, 8192 / 100, 16384 / 200)
+    server.set_batching(*OPEN_LOOP_BATCHING)
     for load in (0.5, 0.8):
         rate = load * sat["qps"]
-        # The replay holds a whole trace (host arrays, list ids on the device, their lengths in
-        # pinned memory), so the window is taken in chunks of at most SERVE_OPEN_MAX_QUERIES
-        # queries, each replayed from an idle server with its first `warmup` seconds left out;
-        # the figures are over all chunks (percentiles over every stride-th latency).
-        chunk_s = max(1.0, SERVE_OPEN_MAX_QUERIES / rate - warmup)
-        n_chunks = max(1, int(np.ceil(seconds / chunk_s)))
-        win = seconds / n_chunks
-        stride = max(1, int(rate * seconds) // 50_000_000)
-        sample, n_meas, ints_meas, lat_sum, wall_meas, window = [], 0, 0.0, 0.0, 0.0, 0.0
-        for c in range(n_chunks):
-            nq = max(1000, int(rate * (win + warmup)))
-            log("serving open loop %.1fx: chunk %d/%d, %d Poisson arrivals at %.3g queries/s"
-                % (load, c + 1, n_chunks, nq, rate))
-            times, qo, ids = inputs.poisson_queries_flat(nq, rate, lists, seed=97 + int(10 * load) + 1000 * c,
-                                                         distinct=False)
-            lat, wall = server.replay((qo, ids), arrivals=times)
-            keep = times >= warmup
-            kept = lat[keep]
-            n_meas += kept.size
-            ints_meas += float(query_ints(qo.view(np.int64), ids)[keep].sum())
-            lat_sum += float(kept.sum())
-            wall_meas += wall - warmup
-            window += float(times[-1] - warmup)
-            sample.append(kept[::stride].copy())
-            del times, qo, ids, lat, keep, kept
-        sample = np.concatenate(sample)
-        r = {"queries": n_meas, "wall_s": wall_meas, "qps": n_meas / wall_meas, "uint32_per_s": ints_meas / wall_meas,
-             "p50_ms": 1e3 * float(np.percentile(sample, 50)), "p99_ms": 1e3 * float(np.percentile(sample, 99)),
-             "mean_ms": 1e3 * lat_sum / max(1, n_meas), "latency_sample_stride": stride, "chunks": n_chunks,
-             "load": load, "offered_qps": rate, "window_s": window, "warmup_s": warmup}
+        log("serving open loop %.1fx: %.3g queries/s, %.1f s of arrivals" % (load, rate, seconds + warmup))
+        f = server.replay_poisson((bq, bi), rate, seconds + warmup, warmup_s=warmup, seed=97 + int(10 * load))
+        r = {"queries": int(f["queries"]), "wall_s": f["wall_s"], "qps": f["queries"] / f["wall_s"],
+             "uint32_per_s": f["ints"] / f["wall_s"], "p50_ms": 1e3 * f["p50_s"], "p99_ms": 1e3 * f["p99_s"],
+             "mean_ms": 1e3 * f["mean_s"], "generated": int(f["generated"]), "batches": int(f["batches"]),
+             "load": load, "offered_qps": rate, "window_s": seconds, "warmup_s": warmup,
+             "trace_queries": SERVE_TRACE_QUERIES}
+        r["batching"] = {"min_lists": OPEN_LOOP_BATCHING[0], "max_wait_us": OPEN_LOOP_BATCHING[1]}
         opened.append(r)
         log("serving open loop %.1fx: offered %.0f q/s over %.1f s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
-            % (load, rate, window, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+            % (load, rate, seconds, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
+    server.set_batching(1024, 20)
     st = server.stats()
     server.close()
     assert st["err"] == 0, "a served batch reported corrupt input"

@@ -310,6 +310,28 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
                       uint32_t outstanding, double *latency_s, double *wall_s);
 
 /*
+ * svb_server_replay_poisson: an open loop whose arrivals are drawn in the
+ * call, for windows longer than a host trace could hold.  Query i (i = 0, 1,
+ * ...) asks for the lists of trace entry i mod nbase (lists[qoff[e] ..
+ * qoff[e+1]), host arrays, at least one list each) and arrives at the i-th
+ * point of a Poisson process of rate qps queries per second, for `seconds`
+ * of arrivals (exponential gaps: 2^22 draws of a 64-bit Mersenne twister
+ * seeded with `seed`, read in order from a fresh random position every 2^22
+ * queries).  Queries are served like svb_server_replay's (results released
+ * unread); those arriving before warmup_s (< seconds) are served but left
+ * out of the figures.  out[0 .. out_cap) receives, as doubles: queries
+ * measured, their integers, seconds from warmup_s to the last completion,
+ * the 50th and 99th percentile and the mean latency in seconds (arrival to
+ * the host seeing the batch complete; percentiles from 0.1 us bins up to
+ * 0.1 s), queries generated, batches launched.  Returns SVB_OK, or a
+ * negative status as svb_server_replay (SVB_ERR_NOMEM also for a trace entry
+ * larger than the arena's largest free range).  The serving setting is
+ * Section 5's: posting lists decoded per query.
+ */
+int svb_server_replay_poisson(void *server, uint64_t nbase, const uint64_t *qoff, const uint32_t *lists, double qps,
+                              double seconds, double warmup_s, uint64_t seed, double *out, uint32_t out_cap);
+
+/*
  * Decoder variants (the paper's decoder special-cases control bytes of
  * single-byte integers, Section 4).  Bit 0 of a variant: 0 = the general
  * decoder; 1 = also decode every row of 64 blocks whose control bytes are all

@@ -19,6 +19,7 @@ __all__ = [
     "svb_set_kernel_timing", "svb_kernel_times", "svb_autotune_decode_batch", "svb_autotune_encode_batch",
     "svb_set_batch_chunk", "svb_server_create", "svb_server_submit", "svb_server_step", "svb_server_poll",
     "svb_server_release", "svb_server_arena", "svb_server_stats", "svb_server_destroy", "svb_server_replay",
+    "svb_server_replay_poisson",
     "svb_server_set_batching", "svb_seek_index_create", "svb_seek_batch", "svb_select_batch",
     "svb_seek_index_destroy", "svb_append", "svb_delta_append", "svb_autotune_decode", "svb_set_decode_variant",
     "encode", "decode",
@@ -51,7 +52,7 @@ def lib():
         # device pointers and streams the tensors carry (the other one need not even see the GPU).
         import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
-        u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+        u64, u32, vp, i32, f64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         sigs = {
             "svb_control_bytes": (u64, [u64]),
             "svb_max_compressed_bytes": (u64, [u64]),
@@ -74,6 +75,7 @@ def lib():
             "svb_server_stats": (i32, [vp, vp, u32]),
             "svb_server_destroy": (i32, [vp]),
             "svb_server_replay": (i32, [vp, u64, vp, vp, vp, u32, vp, vp]),
+            "svb_server_replay_poisson": (i32, [vp, u64, vp, vp, f64, f64, f64, u64, vp, u32]),
             "svb_server_set_batching": (i32, [vp, u32, u32]),
             "svb_seek_index_create": (i32, [u32, vp, vp, vp, vp, vp, u64, vp, vp]),
             "svb_seek_batch": (i32, [vp, u32, vp, vp, vp, vp, vp, vp]),
@@ -435,6 +437,22 @@ def svb_server_replay(server, picks, arrivals=None, outstanding=0):
                                    None if arr is None else arr.ctypes.data, int(outstanding),
                                    lat.ctypes.data, ctypes.addressof(wall)), "svb_server_replay")
     return lat[:nq], wall.value
+
+
+def svb_server_replay_poisson(server, trace, qps, seconds, warmup_s=0.25, seed=0):
+    """Open loop with arrivals drawn in the call: query i asks for the lists of trace entry
+    i mod nbase (trace = (qoff, ids), entry e asking for ids[qoff[e]:qoff[e+1]]) and arrives at
+    the i-th point of a Poisson process of rate ``qps`` for ``seconds``; queries arriving before
+    ``warmup_s`` are served but not counted.  Returns a dict of the figures."""
+    import numpy as np
+    qoff = np.ascontiguousarray(trace[0], dtype=np.uint64)
+    ids = np.ascontiguousarray(trace[1], dtype=np.uint32)
+    out = np.zeros(8, dtype=np.float64)
+    _check(lib().svb_server_replay_poisson(server, qoff.size - 1, qoff.ctypes.data, ids.ctypes.data, float(qps),
+                                           float(seconds), float(warmup_s), int(seed), out.ctypes.data, 8),
+           "svb_server_replay_poisson")
+    keys = ("queries", "ints", "wall_s", "p50_s", "p99_s", "mean_s", "generated", "batches")
+    return dict(zip(keys, out.tolist()))
 
 
 # ------------------------------------------------------------------ conveniences

@@ -35,6 +35,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
+#include <random>
 #include <thread>
 #include <deque>
 #include <map>
@@ -485,6 +487,45 @@ void destroy(Server *s) {
     delete s;
 }
 
+// One batch of a replayed trace on `slot`: its table built on the device from
+// the lists' counts (pinned host memory) and ids (device memory), the lists'
+// descriptors copied with their output addresses (results back to back from
+// arena offset out_base, in integers), the walk, and the slot's completion
+// event.
+int launch_trace_batch(Server &s, Slot *slot, uint32_t nlists, const uint32_t *h_counts, const uint32_t *d_ids,
+                       uint64_t out_base, uint64_t tasks) {
+    uint32_t *d_base = (uint32_t *)(slot->d_table + table_base_off(slot->cap));
+    uint64_t *d_out = (uint64_t *)(slot->d_table + table_out_off(slot->cap));
+    svb::ServePlanArgs pa;
+    pa.m = nlists;
+    pa.counts = h_counts;
+    pa.out_base = out_base;
+    pa.base = d_base;
+    pa.out_off = d_out;
+    ServeDescArgs d;
+    d.m = nlists;
+    d.list = d_ids;
+    d.base = d_base;
+    d.out_off = d_out;
+    d.pool_desc = s.pool_desc;
+    d.pool_lbase = s.pool_lbase;
+    d.arena = s.arena;
+    d.desc = slot->d_desc;
+    BatchArgs a = {};
+    a.m = nlists;
+    a.lbase = d_base;
+    a.t_cap = tasks;
+    a.desc = slot->d_desc;
+    a.err = slot->d_err;
+    if (svb::launch_serve_plan(pa, slot->stream) != hipSuccess ||
+        svb::launch_serve_desc(d, (uint32_t)tasks, slot->stream) != hipSuccess)
+        return SVB_ERR_HIP;
+    int st = SVB_OK;
+    if (tasks) st = svb::serve_walk(a, s.delta, slot->stream);
+    if (st == SVB_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = SVB_ERR_HIP;
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -766,34 +807,8 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
                     ++b;
                 }
                 const uint32_t nlists = (uint32_t)(qoff[b] - qoff[launched]);
-                uint32_t *d_base = (uint32_t *)(slot->d_table + table_base_off(slot->cap));
-                uint64_t *d_out = (uint64_t *)(slot->d_table + table_out_off(slot->cap));
-                svb::ServePlanArgs pa;
-                pa.m = nlists;
-                pa.counts = h_cnt + (qoff[launched] - qoff[0]);
-                pa.out_base = r0 + pos;
-                pa.base = d_base;
-                pa.out_off = d_out;
-                ServeDescArgs d;
-                d.m = nlists;
-                d.list = d_lists + (qoff[launched] - qoff[0]);
-                d.base = d_base;
-                d.out_off = d_out;
-                d.pool_desc = s->pool_desc;
-                d.pool_lbase = s->pool_lbase;
-                d.arena = s->arena;
-                d.desc = slot->d_desc;
-                BatchArgs a = {};
-                a.m = nlists;
-                a.lbase = d_base;
-                a.t_cap = tasks;
-                a.desc = slot->d_desc;
-                a.err = slot->d_err;
-                if (svb::launch_serve_plan(pa, slot->stream) != hipSuccess ||
-                    svb::launch_serve_desc(d, (uint32_t)tasks, slot->stream) != hipSuccess)
-                    st = SVB_ERR_HIP;
-                if (st == SVB_OK && tasks) st = svb::serve_walk(a, s->delta, slot->stream);
-                if (st == SVB_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = SVB_ERR_HIP;
+                st = launch_trace_batch(*s, slot, nlists, h_cnt + (qoff[launched] - qoff[0]),
+                                        d_lists + (qoff[launched] - qoff[0]), r0 + pos, tasks);
                 if (st != SVB_OK) break;
                 slot->busy = true;
                 slot->seq = s->launches++;
@@ -832,6 +847,280 @@ int svb_server_replay(void *server, uint64_t nq, const uint64_t *qoff, const uin
     if (h_cnt) (void)hipHostFree(h_cnt);
     if (wall_s) *wall_s = now_s();
     return st;
+}
+
+// Open loop generated in the call: query i asks for the lists of trace entry
+// i mod nbase and arrives at the i-th point of a Poisson process of rate qps
+// (exponential gaps from a 64-bit Mersenne twister seeded with `seed`, see
+// below) until `seconds` have passed.  The trace's list ids and their counts are set up
+// once, so the host's work per query is an arrival time and, at completion, a
+// histogram bin; batches are runs of consecutive queries that stop at the
+// trace's end.
+int svb_server_replay_poisson(void *server, uint64_t nbase, const uint64_t *qoff, const uint32_t *lists, double qps,
+                              double seconds, double warmup_s, uint64_t seed, double *out, uint32_t out_cap) {
+    Server *s = (Server *)server;
+    if (!s || !qoff || !lists || nbase == 0 || !(qps > 0.0) || !(seconds > 0.0) || !(warmup_s >= 0.0) ||
+        warmup_s >= seconds || (out_cap && !out))
+        return SVB_ERR_INVALID;
+    for (uint64_t i = 0; i < nbase; ++i)
+        if (qoff[i + 1] <= qoff[i] || qoff[i + 1] - qoff[i] > s->max_batch_lists) return SVB_ERR_INVALID;
+    const uint64_t nl = qoff[nbase] - qoff[0];
+    for (uint64_t i = 0; i < nl; ++i)
+        if (lists[qoff[0] + i] >= s->m) return SVB_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(s->mu);
+    (void)hipSetDevice(s->device);
+    if (!s->completed_replay.empty()) return SVB_ERR_INVALID;
+    int st = SVB_OK;
+    const std::deque<uint32_t> none;
+    while (!s->waiting.empty() || !s->admitted.empty()) {
+        if ((st = step_locked(*s, true, none)) != SVB_OK) return st;
+        if (!s->waiting.empty() && s->admitted.empty() &&
+            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot &sl) { return sl.busy; }))
+            return SVB_ERR_NOMEM;
+    }
+    auto big = s->free_ranges.end();
+    for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it)
+        if (big == s->free_ranges.end() || it->second > big->second) big = it;
+    if (big == s->free_ranges.end()) return SVB_ERR_NOMEM;
+    const uint64_t r0 = big->first, R = big->second;
+    // every trace entry sized once: output integers and segments; an entry
+    // that can never be admitted refuses the call before anything runs
+    std::vector<uint64_t> eints(nbase), etasks(nbase);
+    const uint32_t *cnt = s->counts32.data();
+    for (uint64_t e = 0; e < nbase; ++e) {
+        uint64_t ints = 0, tasks = 0;
+        for (uint64_t i = qoff[e]; i < qoff[e + 1]; ++i) {
+            const uint32_t c = cnt[lists[i]];
+            ints += c;
+            tasks += (c + kSegInts - 1) / kSegInts;
+        }
+        if (ints > R || ints >= kBatchIntsMax) return SVB_ERR_NOMEM;
+        eints[e] = ints;
+        etasks[e] = tasks;
+    }
+    s->free_ranges.erase(big);
+    s->free_ints -= R;
+    const uint64_t in_use_before = s->in_use;
+    uint32_t *d_lists = nullptr, *h_cnt = nullptr;
+    if (hipMalloc((void **)&d_lists, 4 * nl) != hipSuccess) st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && hipHostMalloc((void **)&h_cnt, 4 * nl, hipHostMallocDefault) != hipSuccess)
+        st = SVB_ERR_NOMEM;
+    if (st == SVB_OK && hipMemcpy(d_lists, lists + qoff[0], 4 * nl, hipMemcpyHostToDevice) != hipSuccess)
+        st = SVB_ERR_HIP;
+    if (st == SVB_OK)
+        for (uint64_t i = 0; i < nl; ++i) h_cnt[i] = cnt[lists[qoff[0] + i]];
+
+    struct Batch {
+        uint64_t q0, q1, off, len;
+        Slot *slot;
+        bool done;
+    };
+    std::deque<Batch> fifo;
+    uint64_t head = 0;
+    auto ring_space = [&](uint64_t need_first, uint64_t *pos) -> uint64_t {
+        if (fifo.empty()) {
+            *pos = 0;
+            return R;
+        }
+        const uint64_t tail = fifo.front().off;
+        if (head > tail) {
+            if (R - head >= need_first) {
+                *pos = head;
+                return R - head;
+            }
+            *pos = 0;
+            return tail;
+        }
+        *pos = head;
+        return tail > head ? tail - head : 0;
+    };
+    // The gaps: a table of kGaps exponential draws made before the clock
+    // starts, read in order from a fresh random position every kGaps queries
+    // (drawing each gap as it is needed, or reading the table out of order,
+    // costs the launching thread more than a query's share of its time at
+    // tens of millions of queries per second).  Two walkers read the same
+    // sequence: this thread's, which releases arrivals, and the accounting
+    // thread's, which recomputes each query's arrival time when its batch
+    // completes.
+    constexpr uint64_t kGaps = 1ull << 22;
+    std::mt19937_64 rng(seed);
+    std::vector<double> gaps(kGaps);
+    {
+        std::exponential_distribution<double> draw(qps);
+        for (double &g : gaps) g = draw(rng);
+    }
+    struct Arrivals {
+        const std::vector<double> *gaps;
+        std::mt19937_64 rng;
+        uint64_t i = 0, rot = 0;
+        double t = 0.0;  // arrival time of query i
+        void start() {
+            rot = rng();
+            t = (*gaps)[rot & (kGaps - 1)];
+        }
+        void advance() {
+            ++i;
+            if ((i & (kGaps - 1)) == 0) rot = rng();
+            t += (*gaps)[(i + rot) & (kGaps - 1)];
+        }
+    };
+    Arrivals gen{&gaps, rng}, acc_gen{&gaps, rng};
+    gen.start();
+    acc_gen.start();
+    // latency accounting, off this thread: completed batches (queries [q0,
+    // q1), seen complete at tc) go through a single-producer ring
+    constexpr uint64_t kBins = 1000000;  // 0.1 us bins up to 0.1 s, the last bin open
+    constexpr double kBinS = 1e-7;
+    std::vector<uint64_t> hist(kBins, 0);
+    uint64_t measured = 0;
+    double measured_ints = 0.0, lat_sum = 0.0, t_last = 0.0;
+    struct Done {
+        uint64_t q0, q1;
+        double tc;
+    };
+    constexpr uint64_t kRing = 1 << 16;
+    std::vector<Done> ring(kRing);
+    std::atomic<uint64_t> produced{0}, consumed{0};
+    std::atomic<bool> finished{false};
+    std::thread accountant([&] {
+        uint64_t c = 0;
+        for (;;) {
+            const uint64_t p = produced.load(std::memory_order_acquire);
+            if (c == p) {
+                if (finished.load(std::memory_order_acquire) && c == produced.load(std::memory_order_acquire)) break;
+                __builtin_ia32_pause();
+                continue;
+            }
+            for (; c < p; ++c) {
+                const Done d = ring[c & (kRing - 1)];
+                const uint64_t e_first = d.q0 % nbase;  // a batch never wraps the trace
+                for (uint64_t q = d.q0; q < d.q1; ++q, acc_gen.advance()) {
+                    const double ta = acc_gen.t;
+                    if (ta < warmup_s) continue;
+                    const double lat = d.tc - ta;
+                    const uint64_t bin = (uint64_t)(lat * (1.0 / kBinS));
+                    ++hist[bin < kBins ? bin : kBins - 1];
+                    ++measured;
+                    measured_ints += (double)eints[e_first + (q - d.q0)];
+                    lat_sum += lat;
+                }
+                t_last = d.tc;
+            }
+            consumed.store(c, std::memory_order_release);
+        }
+    });
+    std::deque<double> pending;  // arrival times of queries [launched, next)
+    typedef std::chrono::steady_clock clock;
+    const clock::time_point t0 = clock::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    uint64_t next = 0, launched = 0, done = 0, batches = 0, produced_here = 0;
+    while (st == SVB_OK) {
+        const double t = now_s();
+        const uint64_t was = next;
+        while (gen.t <= t && gen.t < seconds) {
+            pending.push_back(gen.t);
+            ++next;
+            gen.advance();
+        }
+        s->stats[3] += next - was;
+        if (gen.t >= seconds && done == next) break;
+        // retire every finished slot; free ring regions in launch order and
+        // hand the batches to the accounting thread
+        for (Batch &b : fifo) {
+            if (b.done) continue;
+            const hipError_t q = hipEventQuery(b.slot->done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                st = SVB_ERR_HIP;
+                break;
+            }
+            b.done = true;
+            b.slot->busy = false;
+        }
+        if (st != SVB_OK) break;
+        if (!fifo.empty() && fifo.front().done) {
+            const double tc = now_s();
+            while (!fifo.empty() && fifo.front().done) {
+                const Batch &b = fifo.front();
+                while (produced_here - consumed.load(std::memory_order_acquire) >= kRing) __builtin_ia32_pause();
+                ring[produced_here & (kRing - 1)] = Done{b.q0, b.q1, tc};
+                produced.store(++produced_here, std::memory_order_release);
+                done += b.q1 - b.q0;
+                s->stats[4] += b.q1 - b.q0;
+                s->in_use -= b.len;
+                fifo.pop_front();
+            }
+            if (fifo.empty()) head = 0;
+        }
+        // launch the arrived queries in order, as many as a batch, the ring's
+        // free region and the trace's end allow, on a free slot
+        if (launched < next) {
+            Slot *slot = nullptr;
+            bool busy = false;
+            for (Slot &sl : s->slots) {
+                if (!sl.busy && !slot) slot = &sl;
+                busy |= sl.busy;
+            }
+            const uint64_t e0 = launched % nbase;
+            const uint64_t avail = std::min<uint64_t>(next - launched, nbase - e0);  // entries before the wrap
+            const bool hold = busy && qoff[e0 + avail] - qoff[e0] < s->min_batch_lists &&
+                              (t - pending.front()) * 1e9 < (double)s->max_wait_ns;
+            uint64_t pos = 0;
+            const uint64_t room = slot && !hold ? ring_space(eints[e0], &pos) : 0;
+            if (slot && !hold && room >= eints[e0]) {
+                uint64_t e = e0, ints = 0, tasks = 0;
+                while (e < e0 + avail && qoff[e + 1] - qoff[e0] <= s->max_batch_lists && ints + eints[e] <= room &&
+                       ints + eints[e] <= kBatchIntsMax) {
+                    ints += eints[e];
+                    tasks += etasks[e];
+                    ++e;
+                }
+                const uint32_t nlists = (uint32_t)(qoff[e] - qoff[e0]);
+                st = launch_trace_batch(*s, slot, nlists, h_cnt + (qoff[e0] - qoff[0]), d_lists + (qoff[e0] - qoff[0]),
+                                        r0 + pos, tasks);
+                if (st != SVB_OK) break;
+                slot->busy = true;
+                slot->seq = s->launches++;
+                fifo.push_back(Batch{launched, launched + (e - e0), pos, ints, slot, false});
+                head = pos + ints;
+                s->in_use += ints;
+                s->stats[7] = std::max(s->stats[7], s->in_use);
+                s->stats[0]++;
+                s->stats[1] += nlists;
+                s->stats[2] += ints;
+                s->stats[5] = std::max(s->stats[5], running_slots(*s, slot));
+                pending.erase(pending.begin(), pending.begin() + (e - e0));
+                launched += e - e0;
+                ++batches;
+            }
+        }
+    }
+    finished.store(true, std::memory_order_release);
+    accountant.join();
+    for (Batch &b : fifo)
+        if (!b.done) {
+            (void)hipEventSynchronize(b.slot->done);
+            b.slot->busy = false;
+        }
+    s->in_use = in_use_before + R;
+    arena_free(*s, r0, R);
+    if (d_lists) (void)hipFree(d_lists);
+    if (h_cnt) (void)hipHostFree(h_cnt);
+    if (st != SVB_OK) return st;
+    auto pct = [&](double f) {
+        const uint64_t want = (uint64_t)std::ceil(f * (double)measured);
+        uint64_t acc = 0;
+        for (uint64_t b = 0; b < kBins; ++b) {
+            acc += hist[b];
+            if (acc >= want && acc) return ((double)b + 0.5) * kBinS;
+        }
+        return 0.0;
+    };
+    const double wall = t_last > warmup_s ? t_last - warmup_s : 0.0;
+    const double res[8] = {(double)measured, measured_ints, wall, pct(0.5), pct(0.99),
+                           measured ? lat_sum / (double)measured : 0.0, (double)next, (double)batches};
+    for (uint32_t i = 0; i < out_cap; ++i) out[i] = i < 8 ? res[i] : 0.0;
+    return SVB_OK;
 }
 
 int svb_server_set_batching(void *server, uint32_t min_lists, uint32_t max_wait_us) {

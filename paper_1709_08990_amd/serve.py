@@ -10,6 +10,7 @@ import time
 import numpy as np
 
 from . import (svb_server_create, svb_server_destroy, svb_server_poll, svb_server_release, svb_server_replay,
+               svb_server_replay_poisson,
                svb_server_set_batching, svb_server_stats, svb_server_step, svb_server_submit)
 
 
@@ -51,6 +52,11 @@ class Server:
         """Native load generator: open loop at ``arrivals`` or closed loop with ``outstanding``
         queries in flight; results are released unread.  Returns (latencies, wall seconds)."""
         return svb_server_replay(self.handle, picks, arrivals, outstanding)
+
+    def replay_poisson(self, trace, qps, seconds, warmup_s=0.25, seed=0):
+        """Native open loop with Poisson arrivals drawn in the call over a trace used cyclically;
+        returns the figures (queries, ints, wall_s, p50_s, p99_s, mean_s, generated, batches)."""
+        return svb_server_replay_poisson(self.handle, trace, qps, seconds, warmup_s, seed)
 
     def close(self):
         if self.handle:

@@ -178,3 +178,48 @@ def test_replay_open_and_closed_loop():
     np.testing.assert_array_equal(read_result(server, off, n), expected(lists, starts, True, p))
     server.release(7)
     server.close()
+
+
+def test_replay_poisson_open_loop():
+    """Arrivals drawn in the call over a trace used cyclically: the generated count is a Poisson
+    draw around qps x seconds, every generated query completes, the figures are consistent, and
+    ordinary queries queued before it and after it still get the oracle's results."""
+    lists, starts, counts, dev = make_pool(2_000, 1_500_000, 1 << 15, True, seed=95)
+    server = serve.Server(dev["counts"], dev["in_off"], dev["in_bytes"], dev["streams"], dev["starts"],
+                          arena_bytes=4 << 20, slots=4, max_batch_lists=512)
+    _, qoff, ids = inputs.poisson_queries_flat(700, 1.0, len(lists), seed=96)
+    mine = {200 + q: ids[qoff[q]:qoff[q + 1]] for q in range(3)}
+    for qid, p in mine.items():
+        server.submit(qid, p)
+    qps, seconds, warmup = 30_000.0, 1.0, 0.2
+    log_case("serve replay poisson", "qps=%g" % qps, "seconds=%g" % seconds)
+    r = server.replay_poisson((qoff, ids), qps, seconds, warmup_s=warmup, seed=7)
+    got = {}
+    while len(got) < len(mine):
+        server.step(block=True)
+        for qid, off, n in server.poll():
+            got[qid] = read_result(server, off, n)
+            server.release(qid)
+    for qid, p in mine.items():
+        np.testing.assert_array_equal(got[qid], expected(lists, starts, True, p), err_msg="query %d" % qid)
+    gen = r["generated"]
+    assert abs(gen - qps * seconds) < 6 * np.sqrt(qps * seconds)
+    assert abs(r["queries"] - qps * (seconds - warmup)) < 6 * np.sqrt(qps * seconds)
+    assert 0 < r["p50_s"] <= r["p99_s"] < 0.1 and r["mean_s"] > 0 and r["wall_s"] > 0 and r["batches"] >= 1
+    st = server.stats()
+    assert st["completed"] == gen + len(mine) and st["err"] == 0 and st["arena_in_use_ints"] == 0
+    # the trace is used cyclically: query i asks for entry i mod 700
+    per_entry = np.add.reduceat(counts[ids], qoff[:-1].astype(np.int64))
+    n = int(gen)
+    want = int(per_entry.sum()) * (n // 700) + int(per_entry[: n % 700].sum())
+    assert st["integers"] == want + sum(int(counts[p].sum()) for p in mine.values())
+    p = ids[qoff[9]:qoff[10]]
+    server.submit(9, p)
+    out = []
+    while not out:
+        server.step(block=True)
+        out = server.poll()
+    (_, off, n2), = out
+    np.testing.assert_array_equal(read_result(server, off, n2), expected(lists, starts, True, p))
+    server.release(9)
+    server.close()
