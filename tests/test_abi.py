@@ -69,6 +69,21 @@ def test_argument_errors_are_synchronous():
     assert L.svb_copy_u32(4, 4098, 4096, None) == -1
 
 
+def test_serving_replay_argument_errors():
+    """A null server or a bad trace or rate is refused before any HIP call."""
+    L = svb.lib()
+    q = (ctypes.c_uint64 * 3)(0, 2, 3)
+    ids = (ctypes.c_uint32 * 3)(1, 2, 3)
+    out = (ctypes.c_double * 8)()
+    assert L.svb_server_replay_poisson(None, 2, q, ids, 1e6, 1.0, 0.1, 1, out, 8) == -1
+    assert L.svb_server_replay(None, 2, q, ids, None, 4, out, None) == -1
+    srv = ctypes.c_void_p(4096)  # never dereferenced: the checks below fail first
+    assert L.svb_server_replay_poisson(srv, 0, q, ids, 1e6, 1.0, 0.1, 1, out, 8) == -1     # empty trace
+    assert L.svb_server_replay_poisson(srv, 2, q, ids, 0.0, 1.0, 0.1, 1, out, 8) == -1     # rate
+    assert L.svb_server_replay_poisson(srv, 2, q, ids, 1e6, 1.0, 1.0, 1, out, 8) == -1     # warm-up >= window
+    assert L.svb_server_replay_poisson(srv, 2, q, ids, 1e6, 1.0, 0.1, 1, None, 8) == -1    # no output
+
+
 def test_comparison_format_sizes_and_argument_errors():
     """VByte and varint-GB entry points: worst-case sizes, and the checks that return before any
     HIP call."""
