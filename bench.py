@@ -1152,7 +1152,7 @@ def main():
                     help="length of each open-loop serving window (seconds of arrivals)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"))
     ap.add_argument("--counter-command", default="rocprofv3 --pmc {COUNTER} --output-format csv -d "
-                    "gpurun_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
+                    "prof_out/pmc_{COUNTER} -o p -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
                     "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control --no-compare")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
                     help="OUT_MD TITLE CSV [CSV ...]: summary of rocprofv3 --pmc runs (every kernel); the "
@@ -1162,7 +1162,7 @@ def main():
                     help="with --summarize-pmc: only kernels whose name holds this fragment (repeatable)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "OUT_MD", "TITLE"))
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d "
-                    "gpurun_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
+                    "prof_out/prof_kt -o kt -- python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline "
                     "--no-2p28 --no-batched --no-serving --no-seek --no-append --no-zero-control --no-compare")
     ap.add_argument("--trace-bench-json", default=None,
                     help="bench line printed by the traced command (for --summarize-trace)")
