@@ -837,7 +837,6 @@ def latency_summary(lat, ints, wall):
 
 
 SERVE_TRACE_QUERIES = 1 << 22  # queries of the open loops' trace, used cyclically
-OPEN_LOOP_BATCHING = (4096, 50)  # lists, microseconds
 
 
 def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_600_000_000, cap=1 << 22,
@@ -914,9 +913,6 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
     # open loop: Poisson arrivals drawn in the replay itself over a trace of SERVE_TRACE_QUERIES
     # queries used cyclically, so a window of any length needs no host trace
     _, bq, bi = inputs.poisson_queries_flat(SERVE_TRACE_QUERIES, 1.0, lists, seed=97, distinct=False)
-    # batches held to 4096 lists or 50 us while another is on the device: the policy that kept the
-    # tail lowest in a sweep of open loops (1024 / 20 us, 4096 / 50, 8192 / 100, 16384 / 200)
-    server.set_batching(*OPEN_LOOP_BATCHING)
     for load in (0.5, 0.8):
         rate = load * sat["qps"]
         log("serving open loop %.1fx: %.3g queries/s, %.1f s of arrivals" % (load, rate, seconds + warmup))
@@ -926,11 +922,10 @@ def measure_serving(svb, torch, np, inputs, seconds, lists=1_000_000, total=1_60
              "mean_ms": 1e3 * f["mean_s"], "generated": int(f["generated"]), "batches": int(f["batches"]),
              "load": load, "offered_qps": rate, "window_s": seconds, "warmup_s": warmup,
              "trace_queries": SERVE_TRACE_QUERIES}
-        r["batching"] = {"min_lists": OPEN_LOOP_BATCHING[0], "max_wait_us": OPEN_LOOP_BATCHING[1]}
+        r["batching"] = {"min_lists": 1024, "max_wait_us": 20}  # the server's defaults
         opened.append(r)
         log("serving open loop %.1fx: offered %.0f q/s over %.1f s, %.3g ints/s, p50 %.3f ms, p99 %.3f ms"
             % (load, rate, seconds, r["uint32_per_s"], r["p50_ms"], r["p99_ms"]))
-    server.set_batching(1024, 20)
     st = server.stats()
     server.close()
     assert st["err"] == 0, "a served batch reported corrupt input"
