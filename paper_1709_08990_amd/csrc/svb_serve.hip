@@ -1010,11 +1010,14 @@ int svb_server_replay_poisson(void *server, uint64_t nbase, const uint64_t *qoff
         }
     });
     // arrival times of queries [launched, next), by query number modulo
-    // kPending (a double-ended queue here, allocating and freeing as queries
-    // came and went, let the open loop fall behind at 40M queries/s: p99
-    // 8-100 ms against 0.17-0.21 ms with this ring)
-    constexpr uint64_t kPending = 1ull << 26;
-    std::vector<double> pending(kPending);
+    // pend_cap: one second of arrivals, at least 2^16 and at most 2^26
+    // entries (a longer backlog holds further arrivals back, their latency
+    // still counted from their arrival times).  A double-ended queue here,
+    // allocating and freeing as queries came and went, let the open loop fall
+    // behind at 40M queries/s: p99 8-100 ms against 0.17-0.21 ms with the ring.
+    uint64_t pend_cap = 1ull << 16;
+    while (pend_cap < (1ull << 26) && (double)pend_cap < qps) pend_cap <<= 1;
+    std::vector<double> pending(pend_cap);
     typedef std::chrono::steady_clock clock;
     const clock::time_point t0 = clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
@@ -1022,8 +1025,8 @@ int svb_server_replay_poisson(void *server, uint64_t nbase, const uint64_t *qoff
     while (st == SVB_OK) {
         const double t = now_s();
         const uint64_t was = next;
-        while (gen.t <= t && gen.t < seconds && next - launched < kPending) {
-            pending[next & (kPending - 1)] = gen.t;
+        while (gen.t <= t && gen.t < seconds && next - launched < pend_cap) {
+            pending[next & (pend_cap - 1)] = gen.t;
             ++next;
             gen.advance();
         }
@@ -1069,7 +1072,7 @@ int svb_server_replay_poisson(void *server, uint64_t nbase, const uint64_t *qoff
             const uint64_t e0 = launched % nbase;
             const uint64_t avail = std::min<uint64_t>(next - launched, nbase - e0);  // entries before the wrap
             const bool hold = busy && qoff[e0 + avail] - qoff[e0] < s->min_batch_lists &&
-                              (t - pending[launched & (kPending - 1)]) * 1e9 < (double)s->max_wait_ns;
+                              (t - pending[launched & (pend_cap - 1)]) * 1e9 < (double)s->max_wait_ns;
             uint64_t pos = 0;
             const uint64_t room = slot && !hold ? ring_space(eints[e0], &pos) : 0;
             if (slot && !hold && room >= eints[e0]) {
